@@ -1,0 +1,216 @@
+/*
+ * rsfde.h -- C ABI of the MI355X (gfx950) solver for the quasi-compact
+ * Crank-Nicolson discretisation of the variable-coefficient Riesz space
+ * fractional diffusion equation, solved at every time step by GMRES(m) with the
+ * sine-transform (tau) preconditioner.
+ *
+ * Problem (Section 1, eq. RSFDE): e(x,t) u_t = sum_i kappa_i d^{alpha_i} u / d|x_i|^{alpha_i} + f
+ * on prod_i (lo_i, hi_i) x (0, T], u = 0 on the boundary, u(x,0) = psi(x),
+ * 1 < alpha_i < 2, kappa_i >= 0 with sum_i kappa_i > 0, e bounded with positive minimum.
+ *
+ * Scheme (Section 2, eq. tls): with N_i interior points per axis,
+ * h_i = (hi_i - lo_i)/(N_i + 1) and dt = T/M, every step solves
+ *     A u^{(m+1)} = b^{(m)},  A = B_alpha E^{(m+1/2)} + S_alpha,
+ *     b^{(m)} = (B_alpha E^{(m+1/2)} - S_alpha) u^{(m)} + dt F^{(m+1/2)},
+ * where B_alpha = B_{alpha_d} x ... x B_{alpha_1} (eq. Ha, tridiagonal factors),
+ * E = diag(e(grid, t_{m+1/2})), S_alpha the d-level symmetric Toeplitz matrix of
+ * eq. Salpha with eta_i = kappa_i dt / (2 h_i^{alpha_i}) and the FCD weights of eq. eq0,
+ * and F the compact operator applied to f (eq. eq2.2, Appendix A).
+ *
+ * Solver (Section 3): left-preconditioned GMRES(m) on the one-sided system
+ * (eq. one-sided), which is GMRES on A u = b with preconditioner
+ * B_alpha P_alpha = ebar B_alpha + tau(S_alpha) (eqs. Pa, tauSalpha, bard), applied
+ * through the d-dimensional sine transform (eq. diag).  The stopping rule is
+ * ||z_k||_2 <= rtol ||z_0||_2 on the preconditioned residual z (Section 4).
+ *
+ * Memory: every vector argument is DEVICE memory owned by the caller.  Grid
+ * vectors are stored lexicographically with x_1 fastest (Section 2): interior
+ * vectors hold prod_i N_i doubles, closure-grid vectors prod_i (N_i + 2) doubles.
+ * The library never allocates device memory: all its device state lives in the
+ * caller's workspace (sized by rsfde_workspace_size).  It allocates a small host
+ * structure and a little pinned host memory for status read-back, released by
+ * rsfde_destroy.
+ *
+ * Streams: all device work of a handle is enqueued on the hipStream_t given to
+ * rsfde_setup (a void* here; NULL is the default stream).  A handle is not
+ * re-entrant and must not be used from two threads at once.
+ *
+ * Errors: every function returns an int status.  0 is success, negative values
+ * are errors, positive values are warnings.  Argument checks run on the host
+ * before any HIP call, so they behave the same on a machine without a GPU.
+ * No C++ exception crosses this boundary.
+ */
+#ifndef RSFDE_H
+#define RSFDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define RSFDE_OK               0
+#define RSFDE_W_NOT_CONVERGED  1   /* GMRES hit max_cycles (or max_outer); u holds the last iterate */
+#define RSFDE_E_INVALID_ARG   -1   /* a parameter or pointer failed validation */
+#define RSFDE_E_WORKSPACE     -2   /* workspace NULL, misaligned (256 B) or too small */
+#define RSFDE_E_HIP           -3   /* a HIP runtime call failed; rsfde_strerror gives details */
+#define RSFDE_E_NONFINITE     -4   /* a NaN/Inf appeared in a residual norm */
+#define RSFDE_E_UNSUPPORTED   -5   /* N_i + 1 outside the transform sizes built into the library */
+#define RSFDE_E_STATE         -6   /* call order violated, e.g. a step before ebar is known */
+
+/* ---- precision forms ---------------------------------------------------- */
+#define RSFDE_FP64   0  /* every operation in FP64 */
+#define RSFDE_MIXED  1  /* FP32 operator/preconditioner inside GMRES, FP64 Arnoldi,
+                           Givens and norms, FP64 true-residual iterative refinement */
+
+typedef struct rsfde_ctx* rsfde_handle;
+
+/* One problem instance.  Fields beyond the paper's statement are solver settings. */
+typedef struct {
+  int     d;            /* spatial dimension, 1..3 */
+  int64_t n[3];         /* N_i interior points on axis i (N_i + 1 must be 2^p or 3*2^p, 4 <= 2(N_i+1) <= 4096) */
+  double  lo[3], hi[3]; /* the box prod_i (lo_i, hi_i), lo_i < hi_i */
+  double  alpha[3];     /* fractional orders, 1 < alpha_i < 2 */
+  double  kappa[3];     /* diffusion coefficients kappa_i >= 0, sum > 0 */
+  double  dt;           /* time step (T/M), > 0 */
+  double  e_min, e_max; /* e_check and e_hat of eq. dhat; both 0 means "not known yet":
+                           then rsfde_set_ebar must be called, or rsfde_solve pre-scans e */
+  int     restart;      /* GMRES restart length m, 1..64 */
+  double  rtol;         /* relative tolerance on the preconditioned residual, > 0 */
+  int     max_cycles;   /* restarts allowed per step (per inner solve in the mixed form), >= 1 */
+  int     precision;    /* RSFDE_FP64 or RSFDE_MIXED */
+  int     x0_mode;      /* 0: GMRES starts from u^{(m)}; 1: from zero */
+  double  inner_rtol;   /* RSFDE_MIXED: tolerance of each FP32 inner solve (0 -> 1e-5) */
+  int     max_outer;    /* RSFDE_MIXED: refinement sweeps allowed per step (0 -> 30) */
+} rsfde_params;
+
+/* Per-instance result of one step (summed over the steps of rsfde_solve). */
+typedef struct {
+  int    iters;         /* Arnoldi iterations (all cycles; all inner solves in the mixed form) */
+  int    cycles;        /* GMRES cycles */
+  int    outer_sweeps;  /* refinement sweeps (mixed form), else 0 */
+  int    converged;     /* 1 when the stopping rule was met */
+  double beta0;         /* ||z_0||_2 of the (last) step */
+  double rel_pres;      /* final preconditioned residual / beta0 of the (last) step */
+} rsfde_stats;
+
+/* Analytic field families the library can evaluate on the device (synthetic
+ * workloads).  Kinds and the meaning of c[] follow the workload descriptions:
+ *   e: CONST c0 | SUMSQ_EXP (sum x_i^2 + exp(-t))/c0 | POLY_T c0 + c1 (1 + c2 t) prod x_i^c3
+ *      | SINPROD_COS c0 + c1 prod sin(pi x_i) cos t | SINE_FIELD c0 + c1 (1 + g/sum|a|)/2
+ *   f: ZERO | MANUFACTURED (u = c0 exp(-t) prod x_i^c1 (1 - x_i)^c1 on the unit box,
+ *      f = e u_t - sum_i kappa_i d^{alpha_i} u, e the instance's e field) | SINE_MODES g
+ *   psi: ZERO | MANUFACTURED u(x, 0)
+ * with g = sum_K a_K prod_i sin(k_i pi x_i), amplitudes a (host array of
+ * modes^d values, k_1 fastest, mode numbers from 1). */
+#define RSFDE_FIELD_ZERO          0
+#define RSFDE_FIELD_CONST         1
+#define RSFDE_FIELD_SUMSQ_EXP     2
+#define RSFDE_FIELD_POLY_T        3
+#define RSFDE_FIELD_SINPROD_COS   4
+#define RSFDE_FIELD_SINE_FIELD    5
+#define RSFDE_FIELD_MANUFACTURED  6
+#define RSFDE_FIELD_SINE_MODES    7
+
+typedef struct {
+  int           kind;
+  double        c[4];
+  int           modes;          /* K <= 8 for the mode families, else 0 */
+  const double* amp;            /* host pointer to K^d amplitudes (copied), or NULL */
+  int           time_dependent; /* 0 lets the library evaluate the field once */
+} rsfde_field;
+
+#define RSFDE_WHICH_E    0  /* e on the interior grid */
+#define RSFDE_WHICH_F    1  /* f on the closure grid */
+#define RSFDE_WHICH_PSI  2  /* psi on the interior grid */
+
+/* Sample callback for rsfde_solve: fill e(interior, t) and f(closure, t) for
+ * one instance at t = t_{m+1/2}, enqueueing work on `stream`; return 0 on success. */
+typedef int (*rsfde_sample_fn)(void* ctx, int instance, double t,
+                               double* e_interior, double* f_closure, void* stream);
+
+/* ---- entry points ------------------------------------------------------- */
+
+/* Bytes of device workspace needed for `count` instances p[0..count-1]
+ * (count >= 1; count > 1 is the batched form, all instances stepping together).
+ * Validates p (RSFDE_E_INVALID_ARG / RSFDE_E_UNSUPPORTED).  Host only. */
+int rsfde_workspace_size(const rsfde_params* p, int count, size_t* bytes);
+
+/* Validate, partition the caller's device workspace (256-byte aligned, at least
+ * rsfde_workspace_size bytes; owned by the caller and kept alive until
+ * rsfde_destroy) and build the per-axis coefficient tables on the device: FCD
+ * weights s_k (eq. eq0 recurrence), the circulant spectrum of the Toeplitz
+ * factors, the tau eigenvalues q (eq. q) and the B eigenvalues (Lemma Heig).
+ * The preconditioner does not depend on the step (Section 3 remark), so this runs once. */
+int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
+                void* stream, rsfde_handle* out);
+
+/* Set e_check / e_hat (eq. dhat) of one instance; ebar = (e_min + e_max)/2 (eq. bard). */
+int rsfde_set_ebar(rsfde_handle h, int instance, double e_min, double e_max);
+
+/* One Crank-Nicolson step for every instance: given e at t_{m+1/2} on the interior
+ * and f at t_{m+1/2} on the closure grid (device pointers per instance, t_m = m dt is
+ * informational), overwrite u[i] = u^{(m)} with u^{(m+1)}.  stats (host array of
+ * `count`, may be NULL) receives per-instance counters.  Synchronises the stream
+ * before returning.  Returns the worst status over the instances. */
+int rsfde_step(rsfde_handle h, double t_m, const double* const* e_half,
+               const double* const* f_half, double* const* u, rsfde_stats* stats);
+
+/* M steps from t = 0.  sample == NULL uses the fields registered with
+ * rsfde_set_fields.  When an instance's e_min = e_max = 0 the e field is first
+ * sampled at all M midpoints to get ebar.  u[i] holds psi on entry, u^{(M)} on exit;
+ * stats accumulate iterations over the steps. */
+int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx,
+                double* const* u, rsfde_stats* stats);
+
+/* Release the host state of a handle (not the caller's workspace). */
+int rsfde_destroy(rsfde_handle h);
+
+/* Human-readable text for a status code (includes the last HIP error for RSFDE_E_HIP). */
+const char* rsfde_strerror(int status);
+
+/* ---- built-in synthetic fields ------------------------------------------ */
+
+/* Register the analytic e, f and psi families of one instance (copies the specs). */
+int rsfde_set_fields(rsfde_handle h, int instance, const rsfde_field* e,
+                     const rsfde_field* f, const rsfde_field* psi);
+
+/* Evaluate a registered field of one instance at time t into `out` (device):
+ * which = RSFDE_WHICH_E (interior), RSFDE_WHICH_F (closure grid), RSFDE_WHICH_PSI. */
+int rsfde_eval_field(rsfde_handle h, int instance, int which, double t, double* out);
+
+/* ---- operator entry points (single instance; device pointers; on the handle's stream) */
+
+/* out = A v = B_alpha (e .* v) + S_alpha v (eq. tls). */
+int rsfde_apply_A(rsfde_handle h, int instance, const double* e, const double* v, double* out);
+
+/* out = (B_alpha P_alpha)^{-1} r = S diag(1/mu) S r, the sine-transform solve with the
+ * tau preconditioner (eqs. Pa, tauSalpha, diag); needs ebar to be set. */
+int rsfde_apply_prec(rsfde_handle h, int instance, const double* r, double* out);
+
+/* out = F = (H_{alpha_d} ... H_{alpha_1}) f restricted to the interior, from f on the
+ * closure grid (eq. eq2.2, Appendix A). */
+int rsfde_compute_F(rsfde_handle h, int instance, const double* f_closure, double* out);
+
+/* out = b = B_alpha (e .* u) - S_alpha u + dt F (eq. tls). */
+int rsfde_rhs(rsfde_handle h, int instance, const double* e, const double* F,
+              const double* u, double* out);
+
+/* Copy the setup tables of one axis to host arrays of length N_axis (any may be
+ * NULL): FCD weights s_0..s_{N-1}, tau eigenvalues q_0..q_{N-1} (eq. q, obtained on
+ * the device from the circulant spectrum) and B eigenvalues lambda_1..lambda_N. */
+int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* q,
+                     double* lambda);
+
+/* Enable (1) or disable (0) per-kernel HIP-event timing of the transform passes;
+ * rsfde_get_timing returns the number of timed pass launches, their summed
+ * milliseconds and summed algorithmic HBM bytes since the last enable. */
+int rsfde_set_timing(rsfde_handle h, int enable);
+int rsfde_get_timing(rsfde_handle h, long long* launches, double* ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSFDE_H */

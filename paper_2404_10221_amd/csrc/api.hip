@@ -1,0 +1,1019 @@
+// Host runtime of the C ABI declared in include/rsfde.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "fields.h"
+#include "krylov.h"
+#include "pass.h"
+#include "pass_sizes.h"
+#include "rsfde.h"
+#include "setup.h"
+
+// ---------------------------------------------------------------------------
+// per-length dispatch
+// ---------------------------------------------------------------------------
+#define RSFDE_DECL(L)                                                                        \
+  template <>                                                                                \
+  hipError_t launch_pass_L<double, L>(const PassArgs&, bool, hipStream_t);                  \
+  template <>                                                                                \
+  hipError_t launch_pass_L<float, L>(const PassArgs&, bool, hipStream_t);                   \
+  template <>                                                                                \
+  hipError_t launch_spectrum_L<L>(const double*, int, const cpx<double>*, double*, float*,  \
+                                  double*, hipStream_t);
+RSFDE_FOR_EACH_L(RSFDE_DECL)
+#undef RSFDE_DECL
+
+static bool supported_L(int L) {
+  switch (L) {
+#define RSFDE_CASE(LL) case LL:
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+static hipError_t launch_pass(int L, bool fp32, const PassArgs& a, bool strided, hipStream_t s) {
+  switch (L) {
+#define RSFDE_CASE(LL) \
+  case LL:             \
+    return fp32 ? launch_pass_L<float, LL>(a, strided, s) : launch_pass_L<double, LL>(a, strided, s);
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+static void pass_shape_rt(int L, bool fp32, bool strided, int* nt, int* ppt) {
+  switch (L) {
+#define RSFDE_CASE(LL)                             \
+  case LL:                                         \
+    if (fp32) pass_shape<float, LL>(strided, nt, ppt); \
+    else pass_shape<double, LL>(strided, nt, ppt);     \
+    return;
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  *nt = 0;
+  *ppt = 0;
+}
+
+hipError_t launch_spectrum(int L, const double* s, int N, const cpx<double>* tw64, double* chat64,
+                           float* chat32, double* q, hipStream_t st) {
+  switch (L) {
+#define RSFDE_CASE(LL) \
+  case LL:             \
+    return launch_spectrum_L<LL>(s, N, tw64, chat64, chat32, q, st);
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// state
+// ---------------------------------------------------------------------------
+namespace {
+
+thread_local hipError_t g_last_hip = hipSuccess;
+thread_local char g_msg[256];
+
+struct Axis {
+  int N = 0, L = 0;
+  double alpha = 0, h = 0, eta = 0;
+  int64_t inner = 1;
+  double *s = nullptr, *chat64 = nullptr, *q = nullptr, *lam64 = nullptr, *wq64 = nullptr;
+  float *chat32 = nullptr, *lam32 = nullptr, *wq32 = nullptr;
+  cpx<double>* tw64 = nullptr;
+  cpx<float>* tw32 = nullptr;
+};
+
+struct FieldHost {
+  rsfde_field spec{};
+  std::vector<double> amp;
+  bool set = false;
+  bool evaluated = false;  // time-independent field already in its buffer
+};
+
+struct Inst {
+  rsfde_params p{};
+  int d = 0;
+  int64_t n = 0, nclo = 0, ldv = 0;
+  Axis ax[3];
+  double *e = nullptr, *f = nullptr, *F = nullptr, *b = nullptr, *V = nullptr;
+  float* e32 = nullptr;
+  void* tmp[4] = {nullptr, nullptr, nullptr, nullptr};
+  GmresState* st = nullptr;
+  unsigned* counters = nullptr;  // [0] Krylov sweeps, [1] update, [2] min/max
+  double* partial = nullptr;
+  double* ebar = nullptr;
+  double* eminmax = nullptr;
+  bool ebar_set = false;
+  double ebar_h = 0;
+  double pscale = 1;
+  // fields
+  FieldHost fe, ff, fpsi;
+  double* famp_e = nullptr;
+  double* famp_f = nullptr;
+  double* fmc = nullptr;
+  double* fsin_e[3] = {nullptr, nullptr, nullptr};
+  double* fsin_f[3] = {nullptr, nullptr, nullptr};
+  int k_prev = 4;
+};
+
+struct TimedPass {
+  hipEvent_t a, b;
+  double bytes;
+};
+
+}  // namespace
+
+struct rsfde_ctx {
+  int count = 0;
+  std::vector<Inst> inst;
+  hipStream_t stream = nullptr;
+  GmresSummary* pinned = nullptr;
+  bool timing = false;
+  std::vector<TimedPass> pending;
+  long long t_launches = 0;
+  double t_ms = 0, t_bytes = 0;
+};
+
+#define CK(x)                          \
+  do {                                 \
+    hipError_t e_ = (x);               \
+    if (e_ != hipSuccess) {            \
+      g_last_hip = e_;                 \
+      return RSFDE_E_HIP;              \
+    }                                  \
+  } while (0)
+
+#define CKS(x)                  \
+  do {                          \
+    int s_ = (x);               \
+    if (s_ < 0) return s_;      \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// validation and layout
+// ---------------------------------------------------------------------------
+static int validate(const rsfde_params* p) {
+  if (!p) return RSFDE_E_INVALID_ARG;
+  if (p->d < 1 || p->d > 3) return RSFDE_E_INVALID_ARG;
+  double ksum = 0.0;
+  int64_t n = 1;
+  for (int i = 0; i < p->d; ++i) {
+    if (p->n[i] < 1 || p->n[i] > 100000) return RSFDE_E_INVALID_ARG;
+    if (!(p->lo[i] < p->hi[i]) || !isfinite(p->lo[i]) || !isfinite(p->hi[i])) return RSFDE_E_INVALID_ARG;
+    if (!(p->alpha[i] > 1.0 && p->alpha[i] < 2.0)) return RSFDE_E_INVALID_ARG;
+    if (!(p->kappa[i] >= 0.0) || !isfinite(p->kappa[i])) return RSFDE_E_INVALID_ARG;
+    ksum += p->kappa[i];
+    n *= p->n[i];
+  }
+  if (!(ksum > 0.0)) return RSFDE_E_INVALID_ARG;
+  if (!(p->dt > 0.0) || !isfinite(p->dt)) return RSFDE_E_INVALID_ARG;
+  const bool eunset = p->e_min == 0.0 && p->e_max == 0.0;
+  if (!eunset && !(p->e_min > 0.0 && p->e_min <= p->e_max && isfinite(p->e_max))) return RSFDE_E_INVALID_ARG;
+  if (p->restart < 1 || p->restart > RSFDE_MAX_RESTART) return RSFDE_E_INVALID_ARG;
+  if (!(p->rtol > 0.0) || !(p->rtol < 1.0)) return RSFDE_E_INVALID_ARG;
+  if (p->max_cycles < 1) return RSFDE_E_INVALID_ARG;
+  if (p->precision != RSFDE_FP64 && p->precision != RSFDE_MIXED) return RSFDE_E_INVALID_ARG;
+  if (p->x0_mode != 0 && p->x0_mode != 1) return RSFDE_E_INVALID_ARG;
+  if (!(p->inner_rtol >= 0.0 && p->inner_rtol < 1.0)) return RSFDE_E_INVALID_ARG;
+  if (p->max_outer < 0) return RSFDE_E_INVALID_ARG;
+  if (n > ((int64_t)1 << 34)) return RSFDE_E_INVALID_ARG;
+  for (int i = 0; i < p->d; ++i) {
+    const int64_t L = 2 * (p->n[i] + 1);
+    if (L > 4096 || !supported_L((int)L)) return RSFDE_E_UNSUPPORTED;
+  }
+  return RSFDE_OK;
+}
+
+struct Bump {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* ptr = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return ptr;
+  }
+};
+
+static void layout(Inst& I, Bump& B) {
+  const rsfde_params& p = I.p;
+  I.d = p.d;
+  I.n = 1;
+  I.nclo = 1;
+  for (int i = 0; i < p.d; ++i) {
+    I.n *= p.n[i];
+    I.nclo *= p.n[i] + 2;
+  }
+  I.ldv = (I.n + 63) / 64 * 64;
+  I.st = B.take<GmresState>(1);
+  I.counters = B.take<unsigned>(64);
+  I.partial = B.take<double>((size_t)1024 * (RSFDE_MAX_RESTART + 1));
+  I.ebar = B.take<double>(1);
+  I.eminmax = B.take<double>(2);
+  for (int i = 0; i < p.d; ++i) {
+    Axis& A = I.ax[i];
+    A.N = (int)p.n[i];
+    A.L = 2 * (A.N + 1);
+    A.s = B.take<double>(A.N);
+    A.q = B.take<double>(A.N);
+    A.lam64 = B.take<double>(A.N);
+    A.wq64 = B.take<double>(A.N);
+    A.chat64 = B.take<double>(A.L);
+    A.lam32 = B.take<float>(A.N);
+    A.wq32 = B.take<float>(A.N);
+    A.chat32 = B.take<float>(A.L);
+    A.tw64 = B.take<cpx<double>>(A.L);
+    A.tw32 = B.take<cpx<float>>(A.L);
+  }
+  I.e = B.take<double>(I.n);
+  if (p.precision == RSFDE_MIXED) I.e32 = B.take<float>(I.n);
+  I.f = B.take<double>(I.nclo);
+  I.F = B.take<double>(I.n);
+  I.b = B.take<double>(I.n);
+  for (int k = 0; k < 4; ++k) I.tmp[k] = B.take<double>(I.n);
+  I.V = B.take<double>((size_t)(p.restart + 1) * I.ldv);
+  I.famp_e = B.take<double>(512);
+  I.famp_f = B.take<double>(512);
+  I.fmc = B.take<double>(3 * RSFDE_MC_STRIDE);
+  for (int i = 0; i < p.d; ++i) {
+    I.fsin_e[i] = B.take<double>((size_t)RSFDE_MAXMODES * (p.n[i] + 2));
+    I.fsin_f[i] = B.take<double>((size_t)RSFDE_MAXMODES * (p.n[i] + 2));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass chains
+// ---------------------------------------------------------------------------
+static PassArgs mk_pass(const Inst& I, int axis, int op, bool fp32) {
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  const Axis& A = I.ax[axis];
+  a.op = op;
+  a.N = A.N;
+  a.d = I.d;
+  a.axis = axis;
+  int64_t inner = 1;
+  for (int l = 0; l < axis; ++l) inner *= I.ax[l].N;
+  a.inner = inner;
+  a.npencil = I.n / A.N;
+  int nt, ppt;
+  pass_shape_rt(A.L, fp32, axis > 0, &nt, &ppt);
+  if (axis == 0) {
+    a.tiles_inner = 1;
+    a.ntiles = (a.npencil + ppt - 1) / ppt;
+  } else {
+    a.tiles_inner = (inner + ppt - 1) / ppt;
+    a.ntiles = (a.npencil / inner) * a.tiles_inner;
+  }
+  a.bd = 1.0 - A.alpha / 12.0;
+  a.bo = A.alpha / 24.0;
+  a.eta = A.eta;
+  a.gam = 1.0;
+  a.xcoef = 0.0;
+  a.chat = fp32 ? (const void*)A.chat32 : (const void*)A.chat64;
+  a.tw = fp32 ? (const void*)A.tw32 : (const void*)A.tw64;
+  for (int l = 0; l < 3; ++l) {
+    a.Nax[l] = l < I.d ? I.ax[l].N : 1;
+    a.lam[l] = l < I.d ? (fp32 ? (const void*)I.ax[l].lam32 : (const void*)I.ax[l].lam64) : nullptr;
+    a.wq[l] = l < I.d ? (fp32 ? (const void*)I.ax[l].wq32 : (const void*)I.ax[l].wq64) : nullptr;
+  }
+  a.ebar = I.ebar;
+  a.pscale = I.pscale;
+  return a;
+}
+
+static double pass_bytes(const PassArgs& a, const Inst& I, bool fp32) {
+  const double w = fp32 ? 4.0 : 8.0;
+  const double n = (double)I.n;
+  const double cin = (a.flags & FL_IN64) ? 8.0 : w;
+  const double aout = (a.flags & FL_OUT64) ? 8.0 : w;
+  switch (a.op) {
+    case OP_MV_FIRST:
+      return n * (cin + w + 2 * w);
+    case OP_MV_MID:
+      return n * 4 * w;
+    case OP_MV_LAST: {
+      double b = n * (cin + w + aout);  // Toeplitz input, stencil input (a or e), output
+      if (a.in_x) b += n * 8.0;
+      return b;
+    }
+    default:
+      return n * (cin + aout);
+  }
+}
+
+static int run_pass(rsfde_ctx* h, const Inst& I, const PassArgs& a, bool fp32) {
+  const int L = I.ax[a.axis].L;
+  if (a.ntiles <= 0) return RSFDE_OK;
+  if (a.ntiles > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
+  if (h->timing) {
+    hipEvent_t ea, eb;
+    CK(hipEventCreate(&ea));
+    CK(hipEventCreate(&eb));
+    CK(hipEventRecord(ea, h->stream));
+    CK(launch_pass(L, fp32, a, a.axis > 0, h->stream));
+    CK(hipEventRecord(eb, h->stream));
+    h->pending.push_back(TimedPass{ea, eb, pass_bytes(a, I, fp32)});
+  } else {
+    CK(launch_pass(L, fp32, a, a.axis > 0, h->stream));
+  }
+  return RSFDE_OK;
+}
+
+static int flush_timing(rsfde_ctx* h) {
+  for (auto& tp : h->pending) {
+    float ms = 0.f;
+    CK(hipEventSynchronize(tp.b));
+    CK(hipEventElapsedTime(&ms, tp.a, tp.b));
+    h->t_ms += ms;
+    h->t_bytes += tp.bytes;
+    h->t_launches += 1;
+    (void)hipEventDestroy(tp.a);
+    (void)hipEventDestroy(tp.b);
+  }
+  h->pending.clear();
+  return RSFDE_OK;
+}
+
+enum Chain { CH_APPLY_A = 0, CH_RHS = 1, CH_RESID = 2, CH_OPER = 3 };
+
+// Operator chains along the axes (x_1 first).  CH_APPLY_A: out = A x.
+// CH_RHS: out = B E x - S x + xcoef * xin.  CH_RESID: out = (BP)^{-1}(xin - A x).
+// CH_OPER: out = (BP)^{-1} A (sc * x).  x is FP64; out is FP64.
+static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const double* x,
+                     const double* sc, const double* xin, double xcoef, double* out) {
+  const int d = I.d;
+  const void* e = fp32 ? (const void*)I.e32 : (const void*)I.e;
+  const bool prec = kind == CH_RESID || kind == CH_OPER;
+  const double sgn = kind == CH_RHS ? -1.0 : 1.0;
+  void* const* T = I.tmp;
+  if (d == 1) {
+    PassArgs a = mk_pass(I, 0, OP_MV_LAST, fp32);
+    a.flags = FL_FIRST_IS_LAST | FL_IN64 | FL_OUT64 | (prec ? FL_PREC_FULL : 0);
+    a.in_c = x;
+    a.sc_ptr = sc;
+    a.in_a = e;
+    a.eta = sgn * I.ax[0].eta;
+    a.gam = kind == CH_RESID ? -1.0 : 1.0;
+    a.in_x = xin;
+    a.xcoef = xcoef;
+    a.out_a = out;
+    return run_pass(h, I, a, fp32);
+  }
+  // first axis
+  PassArgs a = mk_pass(I, 0, OP_MV_FIRST, fp32);
+  a.flags = FL_IN64;
+  a.in_c = x;
+  a.sc_ptr = sc;
+  a.in_a = e;
+  a.eta = sgn * I.ax[0].eta;
+  a.out_a = T[0];
+  a.out_c = T[1];
+  CKS(run_pass(h, I, a, fp32));
+  int ia = 0, ic = 1;
+  if (d == 3) {
+    PassArgs m = mk_pass(I, 1, OP_MV_MID, fp32);
+    m.in_a = T[0];
+    m.in_c = T[1];
+    m.eta = sgn * I.ax[1].eta;
+    m.out_a = T[2];
+    m.out_c = T[3];
+    CKS(run_pass(h, I, m, fp32));
+    ia = 2;
+    ic = 3;
+  }
+  PassArgs z = mk_pass(I, d - 1, OP_MV_LAST, fp32);
+  z.in_a = T[ia];
+  z.in_c = T[ic];
+  z.eta = sgn * I.ax[d - 1].eta;
+  z.gam = kind == CH_RESID ? -1.0 : 1.0;
+  z.in_x = xin;
+  z.xcoef = xcoef;
+  if (!prec) {
+    z.flags = FL_OUT64;
+    z.out_a = out;
+    return run_pass(h, I, z, fp32);
+  }
+  z.flags = FL_DST_AFTER;
+  int cur = d == 2 ? 2 : 0;  // holds the transformed w
+  z.out_a = T[cur];
+  CKS(run_pass(h, I, z, fp32));
+  // remaining forward transforms on axes d-2 .. 1, scaling pass on axis 0,
+  // inverse transforms on axes 1 .. d-1
+  auto nxt = [&](int c) { return (c + 1) & 3; };
+  for (int ax = d - 2; ax >= 1; --ax) {
+    PassArgs t = mk_pass(I, ax, OP_DST, fp32);
+    t.in_c = T[cur];
+    t.out_a = T[nxt(cur)];
+    CKS(run_pass(h, I, t, fp32));
+    cur = nxt(cur);
+  }
+  {
+    PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
+    t.in_c = T[cur];
+    t.out_a = T[nxt(cur)];
+    CKS(run_pass(h, I, t, fp32));
+    cur = nxt(cur);
+  }
+  for (int ax = 1; ax <= d - 1; ++ax) {
+    PassArgs t = mk_pass(I, ax, OP_DST, fp32);
+    t.in_c = T[cur];
+    const bool last = ax == d - 1;
+    t.flags = last ? FL_OUT64 : 0;
+    t.out_a = last ? (void*)out : T[nxt(cur)];
+    CKS(run_pass(h, I, t, fp32));
+    cur = nxt(cur);
+  }
+  return RSFDE_OK;
+}
+
+// (BP)^{-1} r for an FP64 r.
+static int run_prec(rsfde_ctx* h, const Inst& I, bool fp32, const double* r, double* out) {
+  const int d = I.d;
+  void* const* T = I.tmp;
+  if (d == 1) {
+    PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
+    t.flags = FL_IN64 | FL_OUT64;
+    t.in_c = r;
+    t.out_a = out;
+    return run_pass(h, I, t, fp32);
+  }
+  int cur = -1;
+  for (int ax = d - 1; ax >= 1; --ax) {
+    PassArgs t = mk_pass(I, ax, OP_DST, fp32);
+    t.flags = cur < 0 ? FL_IN64 : 0;
+    t.in_c = cur < 0 ? (const void*)r : T[cur];
+    const int o = cur < 0 ? 0 : (cur + 1) & 3;
+    t.out_a = T[o];
+    CKS(run_pass(h, I, t, fp32));
+    cur = o;
+  }
+  {
+    PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
+    t.in_c = T[cur];
+    const int o = (cur + 1) & 3;
+    t.out_a = T[o];
+    CKS(run_pass(h, I, t, fp32));
+    cur = o;
+  }
+  for (int ax = 1; ax <= d - 1; ++ax) {
+    PassArgs t = mk_pass(I, ax, OP_DST, fp32);
+    t.in_c = T[cur];
+    const bool last = ax == d - 1;
+    const int o = (cur + 1) & 3;
+    t.flags = last ? FL_OUT64 : 0;
+    t.out_a = last ? (void*)out : T[o];
+    CKS(run_pass(h, I, t, fp32));
+    cur = o;
+  }
+  return RSFDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fields
+// ---------------------------------------------------------------------------
+static FieldDev field_dev(const Inst& I, const FieldHost& F, bool is_e) {
+  FieldDev fd;
+  memset(&fd, 0, sizeof(fd));
+  fd.kind = F.set ? F.spec.kind : RSFDE_FIELD_ZERO;
+  for (int k = 0; k < 4; ++k) fd.c[k] = F.spec.c[k];
+  fd.K = F.spec.modes;
+  fd.a = (int)llround(F.spec.c[1]);
+  double nrm = 0;
+  for (double v : F.amp) nrm += fabs(v);
+  fd.norm = nrm > 0 ? nrm : 1.0;
+  fd.amp = is_e ? I.famp_e : I.famp_f;
+  for (int i = 0; i < 3; ++i) fd.sintab[i] = i < I.d ? (is_e ? I.fsin_e[i] : I.fsin_f[i]) : nullptr;
+  fd.mc = I.fmc;
+  return fd;
+}
+
+static GridDev grid_dev(const Inst& I, bool closure) {
+  GridDev g;
+  memset(&g, 0, sizeof(g));
+  g.d = I.d;
+  g.closure = closure ? 1 : 0;
+  for (int i = 0; i < I.d; ++i) {
+    g.N[i] = I.ax[i].N;
+    g.lo[i] = I.p.lo[i];
+    g.h[i] = I.ax[i].h;
+    g.kappa[i] = I.p.kappa[i];
+  }
+  g.size = closure ? I.nclo : I.n;
+  return g;
+}
+
+static int eval_field(rsfde_ctx* h, Inst& I, int which, double t, double* out) {
+  FieldDev fe = field_dev(I, I.fe, true);
+  FieldDev ff = field_dev(I, which == RSFDE_WHICH_PSI ? I.fpsi : I.ff, false);
+  if (which == RSFDE_WHICH_PSI) {
+    ff.a = (int)llround(I.fpsi.spec.c[1]);
+  }
+  CK(fields_eval(fe, ff, which, grid_dev(I, which == RSFDE_WHICH_F), t, out, h->stream));
+  return RSFDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one step of one instance
+// ---------------------------------------------------------------------------
+static int read_summary(rsfde_ctx* h, const Inst& I, GmresSummary* out) {
+  CK(hipMemcpyAsync(h->pinned, &I.st->sum, sizeof(GmresSummary), hipMemcpyDeviceToHost, h->stream));
+  CK(hipStreamSynchronize(h->stream));
+  *out = *h->pinned;
+  if (h->timing) CKS(flush_timing(h));
+  return RSFDE_OK;
+}
+
+// Runs one GMRES cycle's iterations (speculatively chunked) after cycle_init.
+static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* S) {
+  const int m = I.p.restart;
+  int j = 0;
+  int chunk = std::max(1, std::min(m, I.k_prev));
+  while (true) {
+    const int jend = std::min(m, j + chunk);
+    for (int jj = j; jj < jend; ++jj) {
+      double* vj = I.V + (int64_t)jj * I.ldv;
+      double* w = I.V + (int64_t)(jj + 1) * I.ldv;
+      CKS(run_chain(h, I, CH_OPER, fp32, vj, I.st->vsc + jj, nullptr, 0.0, w));
+      KryArgs ka;
+      ka.V = I.V;
+      ka.ldv = I.ldv;
+      ka.n = I.n;
+      ka.w = w;
+      ka.st = I.st;
+      ka.partial = I.partial;
+      ka.counter = I.counters;
+      ka.j = jj;
+      ka.m = m;
+      CK(kry_dots(ka, h->stream));
+      CK(kry_orth_dots(ka, h->stream));
+      CK(kry_orth_norm_givens(ka, h->stream));
+    }
+    CK(kry_update(I.V, I.ldv, I.n, x, I.st, I.counters + 1, h->stream));
+    CKS(read_summary(h, I, S));
+    if (S->flag != GM_RUNNING) return RSFDE_OK;
+    j = jend;
+    chunk = 1;
+    if (j >= m) return RSFDE_OK;  // cannot happen: the last Givens step ends the cycle
+  }
+}
+
+static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f_half, double* u,
+                    rsfde_stats* stats) {
+  if (!I.ebar_set) return RSFDE_E_STATE;
+  const rsfde_params& p = I.p;
+  const bool mixed = p.precision == RSFDE_MIXED;
+  if (e_half != I.e) CK(hipMemcpyAsync(I.e, e_half, I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  GridDev gi = grid_dev(I, false);
+  double al[3] = {I.p.alpha[0], I.p.alpha[1], I.p.alpha[2]};
+  CK(compute_F(f_half, gi, al, I.F, h->stream));
+  if (mixed) CK(convert_f64_f32(I.e, I.e32, I.n, h->stream));
+  // b = (B E - S) u + dt F
+  CKS(run_chain(h, I, CH_RHS, false, u, nullptr, I.F, p.dt, I.b));
+  if (p.x0_mode == 1) CK(fill_f64(u, I.n, 0.0, h->stream));
+  rsfde_stats st;
+  memset(&st, 0, sizeof(st));
+  GmresSummary S;
+  memset(&S, 0, sizeof(S));
+  const double inner_rtol = p.inner_rtol > 0.0 ? p.inner_rtol : 1e-5;
+  const int max_outer = p.max_outer > 0 ? p.max_outer : 30;
+  const int max_loops = mixed ? max_outer + 1 : p.max_cycles;
+  int status = RSFDE_W_NOT_CONVERGED;
+  for (int cyc = 0; cyc < max_loops; ++cyc) {
+    // z = (BP)^{-1} (b - A u) in FP64 into V_0
+    CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
+    CK(kry_cycle_init(I.V, I.n, I.st, I.partial, I.counters, cyc == 0 ? 1 : 0, p.rtol, inner_rtol,
+                      mixed ? 1 : 0, h->stream));
+    if (mixed && cyc == max_outer) {
+      // final check only
+      CKS(read_summary(h, I, &S));
+      if (S.flag == GM_CONVERGED) status = RSFDE_OK;
+      break;
+    }
+    CKS(run_cycle(h, I, mixed, u, &S));
+    if (S.flag == GM_NONFINITE) return RSFDE_E_NONFINITE;
+    st.iters += S.k;
+    if (S.k > 0) {
+      st.cycles += 1;
+      I.k_prev = S.k;
+    }
+    if (mixed) {
+      if (S.k == 0 && S.flag == GM_CONVERGED) {
+        status = RSFDE_OK;
+        break;
+      }
+      st.outer_sweeps += 1;
+    } else {
+      if (S.flag == GM_CONVERGED || S.flag == GM_BREAKDOWN) {
+        status = RSFDE_OK;
+        break;
+      }
+    }
+  }
+  if (stats) {
+    stats->iters += st.iters;
+    stats->cycles += st.cycles;
+    stats->outer_sweeps += st.outer_sweeps;
+    stats->converged = status == RSFDE_OK ? 1 : 0;
+    stats->beta0 = S.beta0;
+    stats->rel_pres = S.beta0 > 0 ? (mixed ? S.beta : S.res) / S.beta0 : 0.0;
+  }
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int rsfde_workspace_size(const rsfde_params* p, int count, size_t* bytes) {
+  if (!p || !bytes || count < 1) return RSFDE_E_INVALID_ARG;
+  Bump B{nullptr};
+  for (int i = 0; i < count; ++i) {
+    const int v = validate(&p[i]);
+    if (v != RSFDE_OK) return v;
+    Inst I;
+    I.p = p[i];
+    layout(I, B);
+  }
+  *bytes = (B.off + 255) & ~(size_t)255;
+  return RSFDE_OK;
+}
+
+int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes, void* stream,
+                rsfde_handle* out) {
+  if (!p || !out || count < 1) return RSFDE_E_INVALID_ARG;
+  size_t need = 0;
+  const int v = rsfde_workspace_size(p, count, &need);
+  if (v != RSFDE_OK) return v;
+  if (!workspace || bytes < need || ((uintptr_t)workspace & 255)) return RSFDE_E_WORKSPACE;
+  rsfde_ctx* h = new (std::nothrow) rsfde_ctx();
+  if (!h) return RSFDE_E_INVALID_ARG;
+  h->count = count;
+  h->stream = (hipStream_t)stream;
+  h->inst.resize(count);
+  Bump B{(char*)workspace};
+  int status = RSFDE_OK;
+  hipError_t he = hipHostMalloc((void**)&h->pinned, sizeof(GmresSummary), hipHostMallocDefault);
+  if (he != hipSuccess) {
+    g_last_hip = he;
+    delete h;
+    return RSFDE_E_HIP;
+  }
+  for (int i = 0; i < count && status == RSFDE_OK; ++i) {
+    Inst& I = h->inst[i];
+    I.p = p[i];
+    layout(I, B);
+    double pscale = 1.0;
+    int64_t inner = 1;
+    for (int a = 0; a < I.d; ++a) {
+      Axis& A = I.ax[a];
+      A.alpha = p[i].alpha[a];
+      A.h = (p[i].hi[a] - p[i].lo[a]) / (double)(A.N + 1);
+      A.eta = p[i].kappa[a] * p[i].dt / (2.0 * pow(A.h, A.alpha));
+      A.inner = inner;
+      inner *= A.N;
+      pscale /= (double)A.L;
+      hipError_t e = setup_axis_tables(A.alpha, A.N, A.L, A.eta, A.s, A.tw64, A.tw32, A.chat64,
+                                       A.chat32, A.q, A.lam64, A.lam32, A.wq64, A.wq32, h->stream);
+      if (e != hipSuccess) {
+        g_last_hip = e;
+        status = RSFDE_E_HIP;
+        break;
+      }
+    }
+    I.pscale = pscale;
+    if (status != RSFDE_OK) break;
+    if (kry_state_reset(I.st, I.counters, h->stream) != hipSuccess ||
+        hipMemsetAsync(I.counters, 0, 64 * sizeof(unsigned), h->stream) != hipSuccess) {
+      g_last_hip = hipGetLastError();
+      status = RSFDE_E_HIP;
+      break;
+    }
+    if (!(p[i].e_min == 0.0 && p[i].e_max == 0.0)) {
+      const double eb = 0.5 * (p[i].e_min + p[i].e_max);
+      I.ebar_h = eb;
+      I.ebar_set = true;
+      if (hipMemcpyAsync(I.ebar, &I.ebar_h, sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+        status = RSFDE_E_HIP;
+        break;
+      }
+    }
+  }
+  if (status == RSFDE_OK) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+      g_last_hip = e;
+      status = RSFDE_E_HIP;
+    }
+  }
+  if (status != RSFDE_OK) {
+    (void)hipHostFree(h->pinned);
+    delete h;
+    return status;
+  }
+  *out = h;
+  return RSFDE_OK;
+}
+
+int rsfde_set_ebar(rsfde_handle h, int instance, double e_min, double e_max) {
+  if (!h || instance < 0 || instance >= h->count) return RSFDE_E_INVALID_ARG;
+  if (!(e_min > 0.0 && e_min <= e_max && isfinite(e_max))) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  I.ebar_h = 0.5 * (e_min + e_max);
+  CK(hipMemcpyAsync(I.ebar, &I.ebar_h, sizeof(double), hipMemcpyHostToDevice, h->stream));
+  CK(hipStreamSynchronize(h->stream));
+  I.ebar_set = true;
+  return RSFDE_OK;
+}
+
+int rsfde_step(rsfde_handle h, double t_m, const double* const* e_half, const double* const* f_half,
+               double* const* u, rsfde_stats* stats) {
+  (void)t_m;
+  if (!h || !e_half || !f_half || !u) return RSFDE_E_INVALID_ARG;
+  for (int i = 0; i < h->count; ++i)
+    if (!e_half[i] || !f_half[i] || !u[i]) return RSFDE_E_INVALID_ARG;
+  int worst = RSFDE_OK;
+  for (int i = 0; i < h->count; ++i) {
+    if (stats) memset(&stats[i], 0, sizeof(rsfde_stats));
+    const int s = step_one(h, h->inst[i], e_half[i], f_half[i], u[i], stats ? &stats[i] : nullptr);
+    if (s < 0) return s;
+    if (s > worst) worst = s;
+  }
+  CK(hipStreamSynchronize(h->stream));
+  return worst;
+}
+
+static int builtin_sample(rsfde_ctx* h, Inst& I, double t, bool need_f) {
+  if (!(I.fe.set && !I.fe.spec.time_dependent && I.fe.evaluated)) {
+    CKS(eval_field(h, I, RSFDE_WHICH_E, t, I.e));
+    if (!I.fe.spec.time_dependent) I.fe.evaluated = true;
+  }
+  if (need_f && !(I.ff.set && !I.ff.spec.time_dependent && I.ff.evaluated)) {
+    CKS(eval_field(h, I, RSFDE_WHICH_F, t, I.f));
+    if (!I.ff.spec.time_dependent) I.ff.evaluated = true;
+  }
+  return RSFDE_OK;
+}
+
+int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx, double* const* u,
+                rsfde_stats* stats) {
+  if (!h || M < 0 || !u) return RSFDE_E_INVALID_ARG;
+  for (int i = 0; i < h->count; ++i) {
+    if (!u[i]) return RSFDE_E_INVALID_ARG;
+    if (!sample && !h->inst[i].fe.set) return RSFDE_E_STATE;
+  }
+  if (stats) memset(stats, 0, sizeof(rsfde_stats) * h->count);
+  // ebar pre-scan over all midpoints (eq. dhat) where it is not known yet
+  for (int i = 0; i < h->count; ++i) {
+    Inst& I = h->inst[i];
+    if (I.ebar_set) continue;
+    CK(minmax_reset(I.eminmax, h->stream));
+    const bool tindep = !sample && !I.fe.spec.time_dependent;
+    const int scans = tindep ? std::min(M, 1) : M;
+    for (int m = 0; m < scans; ++m) {
+      const double th = (m + 0.5) * I.p.dt;
+      if (sample) {
+        if (sample(ctx, i, th, I.e, I.f, (void*)h->stream) != 0) return RSFDE_E_INVALID_ARG;
+      } else {
+        CKS(eval_field(h, I, RSFDE_WHICH_E, th, I.e));
+      }
+      CK(minmax_accum(I.e, I.n, I.eminmax, I.partial, I.counters + 2, h->stream));
+    }
+    double mm[2];
+    CK(hipMemcpyAsync(mm, I.eminmax, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    if (!(mm[0] > 0.0) || !isfinite(mm[1])) return RSFDE_E_INVALID_ARG;
+    CKS(rsfde_set_ebar(h, i, mm[0], mm[1]));
+  }
+  int worst = RSFDE_OK;
+  for (int m = 0; m < M; ++m) {
+    for (int i = 0; i < h->count; ++i) {
+      Inst& I = h->inst[i];
+      const double th = (m + 0.5) * I.p.dt;
+      if (sample) {
+        if (sample(ctx, i, th, I.e, I.f, (void*)h->stream) != 0) return RSFDE_E_INVALID_ARG;
+      } else {
+        CKS(builtin_sample(h, I, th, true));
+      }
+      rsfde_stats s1;
+      memset(&s1, 0, sizeof(s1));
+      const int s = step_one(h, I, I.e, I.f, u[i], &s1);
+      if (s < 0) return s;
+      if (s > worst) worst = s;
+      if (stats) {
+        stats[i].iters += s1.iters;
+        stats[i].cycles += s1.cycles;
+        stats[i].outer_sweeps += s1.outer_sweeps;
+        stats[i].converged = (m == 0 ? 1 : stats[i].converged) & s1.converged;
+        stats[i].beta0 = s1.beta0;
+        stats[i].rel_pres = s1.rel_pres;
+      }
+    }
+  }
+  CK(hipStreamSynchronize(h->stream));
+  return worst;
+}
+
+int rsfde_destroy(rsfde_handle h) {
+  if (!h) return RSFDE_E_INVALID_ARG;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& tp : h->pending) {
+    (void)hipEventDestroy(tp.a);
+    (void)hipEventDestroy(tp.b);
+  }
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return RSFDE_OK;
+}
+
+const char* rsfde_strerror(int status) {
+  switch (status) {
+    case RSFDE_OK:
+      return "ok";
+    case RSFDE_W_NOT_CONVERGED:
+      return "GMRES did not reach the tolerance within the allowed cycles (last iterate returned)";
+    case RSFDE_E_INVALID_ARG:
+      return "invalid argument";
+    case RSFDE_E_WORKSPACE:
+      return "workspace missing, misaligned (256 B) or too small";
+    case RSFDE_E_HIP:
+      snprintf(g_msg, sizeof(g_msg), "HIP runtime error: %s", hipGetErrorString(g_last_hip));
+      return g_msg;
+    case RSFDE_E_NONFINITE:
+      return "non-finite residual norm";
+    case RSFDE_E_UNSUPPORTED:
+      return "grid size not supported: N_i + 1 must be 2^p or 3*2^p with 8 <= 2(N_i+1) <= 4096";
+    case RSFDE_E_STATE:
+      return "call order: ebar (e_min/e_max) or the fields are not set";
+    default:
+      return "unknown status";
+  }
+}
+
+int rsfde_set_fields(rsfde_handle h, int instance, const rsfde_field* e, const rsfde_field* f,
+                     const rsfde_field* psi) {
+  if (!h || instance < 0 || instance >= h->count || !e || !f || !psi) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  const int d = I.d;
+  auto chk = [&](const rsfde_field* F, int lo, int hi) -> bool {
+    if (F->kind < lo || F->kind > hi) return false;
+    if (F->kind == RSFDE_FIELD_SINE_FIELD || F->kind == RSFDE_FIELD_SINE_MODES) {
+      if (F->modes < 1 || F->modes > RSFDE_MAXMODES || !F->amp) return false;
+    }
+    return true;
+  };
+  if (!chk(e, RSFDE_FIELD_CONST, RSFDE_FIELD_SINE_FIELD)) return RSFDE_E_INVALID_ARG;
+  if (!(f->kind == RSFDE_FIELD_ZERO || f->kind == RSFDE_FIELD_MANUFACTURED || f->kind == RSFDE_FIELD_SINE_MODES) ||
+      !chk(f, 0, 7))
+    return RSFDE_E_INVALID_ARG;
+  if (!(psi->kind == RSFDE_FIELD_ZERO || psi->kind == RSFDE_FIELD_MANUFACTURED)) return RSFDE_E_INVALID_ARG;
+  if (f->kind == RSFDE_FIELD_MANUFACTURED) {
+    const double a = f->c[1];
+    if (!(a >= 2.0 && a <= 6.0 && a == floor(a))) return RSFDE_E_INVALID_ARG;
+    for (int i = 0; i < d; ++i)
+      if (I.p.lo[i] != 0.0 || I.p.hi[i] != 1.0) return RSFDE_E_INVALID_ARG;
+  }
+  if (psi->kind == RSFDE_FIELD_MANUFACTURED) {
+    const double a = psi->c[1];
+    if (!(a >= 1.0 && a <= 6.0 && a == floor(a))) return RSFDE_E_INVALID_ARG;
+  }
+  if (e->kind == RSFDE_FIELD_SUMSQ_EXP && !(e->c[0] != 0.0)) return RSFDE_E_INVALID_ARG;
+  auto load = [&](FieldHost& H, const rsfde_field* F) {
+    H.spec = *F;
+    H.amp.clear();
+    if (F->amp && F->modes > 0) {
+      int64_t cnt = 1;
+      for (int i = 0; i < d; ++i) cnt *= F->modes;
+      H.amp.assign(F->amp, F->amp + cnt);
+    }
+    H.spec.amp = nullptr;
+    H.set = true;
+    H.evaluated = false;
+  };
+  load(I.fe, e);
+  load(I.ff, f);
+  load(I.fpsi, psi);
+  // device tables
+  if (!I.fe.amp.empty())
+    CK(hipMemcpyAsync(I.famp_e, I.fe.amp.data(), I.fe.amp.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (!I.ff.amp.empty())
+    CK(hipMemcpyAsync(I.famp_f, I.ff.amp.data(), I.ff.amp.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  for (int i = 0; i < d; ++i) {
+    if (I.fe.spec.modes > 0)
+      CK(fields_sintab(I.fe.spec.modes, I.ax[i].N + 2, I.p.lo[i], I.ax[i].h, I.fsin_e[i], h->stream));
+    if (I.ff.spec.modes > 0)
+      CK(fields_sintab(I.ff.spec.modes, I.ax[i].N + 2, I.p.lo[i], I.ax[i].h, I.fsin_f[i], h->stream));
+  }
+  // manufactured source: coefficients of x^a (1-x)^a and its mirror, times the
+  // Riemann-Liouville power-rule factors Gamma(k+1)/Gamma(k+1-alpha)
+  std::vector<double> mc(3 * RSFDE_MC_STRIDE, 0.0);
+  if (f->kind == RSFDE_FIELD_MANUFACTURED) {
+    const int a = (int)llround(f->c[1]);
+    std::vector<double> c(2 * a + 1, 0.0);
+    double binom = 1.0;
+    for (int j = 0; j <= a; ++j) {
+      c[a + j] = (j % 2 ? -1.0 : 1.0) * binom;
+      binom = binom * (a - j) / (j + 1);
+    }
+    for (int i = 0; i < d; ++i) {
+      const double al = I.p.alpha[i];
+      double* row = mc.data() + i * RSFDE_MC_STRIDE;
+      for (int k = 0; k <= 2 * a; ++k) {
+        if (c[k] == 0.0) continue;
+        const double g = tgamma(k + 1.0) / tgamma(k + 1.0 - al);
+        row[k] = c[k] * g;       // left-sided, power x^{k-alpha}
+        row[13 + k] = c[k] * g;  // right-sided: p(1-y) = p(y) for this family
+      }
+      row[26] = -1.0 / (2.0 * cos(al * M_PI / 2.0));
+      row[27] = al;
+    }
+  }
+  CK(hipMemcpyAsync(I.fmc, mc.data(), mc.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  CK(hipStreamSynchronize(h->stream));
+  return RSFDE_OK;
+}
+
+int rsfde_eval_field(rsfde_handle h, int instance, int which, double t, double* out) {
+  if (!h || instance < 0 || instance >= h->count || !out) return RSFDE_E_INVALID_ARG;
+  if (which < RSFDE_WHICH_E || which > RSFDE_WHICH_PSI) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  if (!I.fe.set) return RSFDE_E_STATE;
+  return eval_field(h, I, which, t, out);
+}
+
+int rsfde_apply_A(rsfde_handle h, int instance, const double* e, const double* v, double* out) {
+  if (!h || instance < 0 || instance >= h->count || !e || !v || !out) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  if (e != I.e) CK(hipMemcpyAsync(I.e, e, I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  return run_chain(h, I, CH_APPLY_A, false, v, nullptr, nullptr, 0.0, out);
+}
+
+int rsfde_apply_prec(rsfde_handle h, int instance, const double* r, double* out) {
+  if (!h || instance < 0 || instance >= h->count || !r || !out) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  if (!I.ebar_set) return RSFDE_E_STATE;
+  return run_prec(h, I, false, r, out);
+}
+
+int rsfde_compute_F(rsfde_handle h, int instance, const double* f_closure, double* out) {
+  if (!h || instance < 0 || instance >= h->count || !f_closure || !out) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  double al[3] = {I.p.alpha[0], I.p.alpha[1], I.p.alpha[2]};
+  CK(compute_F(f_closure, grid_dev(I, false), al, out, h->stream));
+  return RSFDE_OK;
+}
+
+int rsfde_rhs(rsfde_handle h, int instance, const double* e, const double* F, const double* u,
+              double* out) {
+  if (!h || instance < 0 || instance >= h->count || !e || !F || !u || !out) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  if (e != I.e) CK(hipMemcpyAsync(I.e, e, I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  return run_chain(h, I, CH_RHS, false, u, nullptr, F, I.p.dt, out);
+}
+
+int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* q, double* lambda) {
+  if (!h || instance < 0 || instance >= h->count) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  if (axis < 0 || axis >= I.d) return RSFDE_E_INVALID_ARG;
+  const Axis& A = I.ax[axis];
+  CK(hipStreamSynchronize(h->stream));
+  if (s) CK(hipMemcpy(s, A.s, A.N * sizeof(double), hipMemcpyDeviceToHost));
+  if (q) CK(hipMemcpy(q, A.q, A.N * sizeof(double), hipMemcpyDeviceToHost));
+  if (lambda) CK(hipMemcpy(lambda, A.lam64, A.N * sizeof(double), hipMemcpyDeviceToHost));
+  return RSFDE_OK;
+}
+
+int rsfde_set_timing(rsfde_handle h, int enable) {
+  if (!h) return RSFDE_E_INVALID_ARG;
+  CKS(flush_timing(h));
+  h->timing = enable != 0;
+  h->t_launches = 0;
+  h->t_ms = 0;
+  h->t_bytes = 0;
+  return RSFDE_OK;
+}
+
+int rsfde_get_timing(rsfde_handle h, long long* launches, double* ms, double* bytes) {
+  if (!h) return RSFDE_E_INVALID_ARG;
+  CK(hipStreamSynchronize(h->stream));
+  CKS(flush_timing(h));
+  if (launches) *launches = h->t_launches;
+  if (ms) *ms = h->t_ms;
+  if (bytes) *bytes = h->t_bytes;
+  return RSFDE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+// LDS-resident complex FFTs of length L = 2(N+1) for pencil batches (gfx950).
+//
+// One length-L transform is owned by T = L/E threads; each thread holds E
+// complex values in registers per stage and runs E/R radix-R butterflies.
+// Stages are Stockham auto-sort passes: stage s with radix R and Ns = product of
+// the earlier radices reads x[j + r L/R], twiddles by W_{Ns R}^{r (j mod Ns)},
+// applies a length-R DFT and writes y[(j/Ns) Ns R + (j mod Ns) + r Ns]; the
+// result comes out in natural order, in place (reads finish before a barrier,
+// writes follow it).
+//
+// The sizes carried are L = 2^p (8..4096) and 3*2^p (12..3072), i.e. the
+// grid sizes N_i + 1 = 2^p or 3*2^p for which the same length serves the
+// circulant embedding of the Toeplitz factors and the odd extension behind the
+// type-I sine transform (Section 3, eq. diag).
+#pragma once
+#include "common.h"
+
+template <int L> struct FftPlan;
+
+#define RSFDE_PLAN(L_, E_, ...)                                                  \
+  template <> struct FftPlan<L_> {                                               \
+    static constexpr int Lv = L_, E = E_, T = L_ / E_;                           \
+    static constexpr int R[] = {__VA_ARGS__};                                    \
+    static constexpr int NS = sizeof(R) / sizeof(int);                           \
+  };
+
+RSFDE_PLAN(8, 8, 8)
+RSFDE_PLAN(12, 12, 4, 3)
+RSFDE_PLAN(16, 16, 16)
+RSFDE_PLAN(24, 12, 4, 3, 2)
+RSFDE_PLAN(32, 16, 16, 2)
+RSFDE_PLAN(48, 12, 4, 4, 3)
+RSFDE_PLAN(64, 16, 16, 4)
+RSFDE_PLAN(96, 12, 4, 4, 3, 2)
+RSFDE_PLAN(128, 16, 16, 8)
+RSFDE_PLAN(192, 12, 4, 4, 4, 3)
+RSFDE_PLAN(256, 16, 16, 16)
+RSFDE_PLAN(384, 12, 4, 4, 4, 3, 2)
+RSFDE_PLAN(512, 8, 8, 8, 8)
+RSFDE_PLAN(768, 12, 4, 4, 4, 4, 3)
+RSFDE_PLAN(1024, 16, 16, 16, 4)
+RSFDE_PLAN(1536, 24, 8, 8, 8, 3)
+RSFDE_PLAN(2048, 16, 16, 16, 8)
+RSFDE_PLAN(3072, 24, 8, 8, 8, 3, 2)
+RSFDE_PLAN(4096, 16, 16, 16, 16)
+#undef RSFDE_PLAN
+
+template <int L, int S> struct StageNs {
+  static constexpr int value = StageNs<L, S - 1>::value * FftPlan<L>::R[S - 1];
+};
+template <int L> struct StageNs<L, 0> { static constexpr int value = 1; };
+
+// ---- small DFTs; DIR = -1 forward (e^{-2 pi i nk/R}), +1 backward ----------
+
+// multiply by e^{DIR i pi/2}: forward -i, backward +i
+template <typename R, int DIR>
+__device__ __forceinline__ cpx<R> rot90(cpx<R> a) {
+  return DIR < 0 ? cpx<R>{a.y, -a.x} : cpx<R>{-a.y, a.x};
+}
+
+template <typename R, int DIR>
+__device__ __forceinline__ void dft2(cpx<R>* v) {
+  cpx<R> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <typename R, int DIR>
+__device__ __forceinline__ void dft3(cpx<R>* v) {
+  const R s3 = (R)0.86602540378443864676;  // sin(2 pi/3)
+  cpx<R> t1 = v[1] + v[2], t2 = v[1] - v[2];
+  cpx<R> m = v[0] - t1 * (R)0.5;
+  // forward: X1 = m - i s3 t2, X2 = m + i s3 t2 ; backward: signs swapped
+  cpx<R> s = rot90<R, DIR>(t2) * s3;
+  v[0] = v[0] + t1;
+  v[1] = m + s;
+  v[2] = m - s;
+}
+
+template <typename R, int DIR>
+__device__ __forceinline__ void dft4(cpx<R>* v) {
+  cpx<R> a0 = v[0] + v[2], a1 = v[0] - v[2];
+  cpx<R> a2 = v[1] + v[3], a3 = rot90<R, DIR>(v[1] - v[3]);
+  v[0] = a0 + a2;
+  v[2] = a0 - a2;
+  v[1] = a1 + a3;
+  v[3] = a1 - a3;
+}
+
+template <typename R, int DIR>
+__device__ __forceinline__ void dft8(cpx<R>* v) {
+  const R h = (R)0.70710678118654752440;
+  cpx<R> e[4] = {v[0], v[2], v[4], v[6]};
+  cpx<R> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<R, DIR>(e);
+  dft4<R, DIR>(o);
+  // W8^1 = (1 + DIR i) h, W8^2 = DIR i, W8^3 = (-1 + DIR i) h
+  cpx<R> o1 = cpx<R>{(o[1].x - (R)DIR * o[1].y) * h, ((R)DIR * o[1].x + o[1].y) * h};
+  cpx<R> o2 = rot90<R, DIR>(o[2]);
+  cpx<R> o3 = cpx<R>{(-o[3].x - (R)DIR * o[3].y) * h, ((R)DIR * o[3].x - o[3].y) * h};
+  v[0] = e[0] + o[0];
+  v[4] = e[0] - o[0];
+  v[1] = e[1] + o1;
+  v[5] = e[1] - o1;
+  v[2] = e[2] + o2;
+  v[6] = e[2] - o2;
+  v[3] = e[3] + o3;
+  v[7] = e[3] - o3;
+}
+
+template <typename R, int DIR>
+__device__ __forceinline__ void dft16(cpx<R>* v) {
+  // 4 x 4 decomposition: inner length-4 DFTs over n2 (stride 4), twiddles
+  // W16^{n1 k2}, outer length-4 DFTs over n1.
+  const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173;
+  const R h = (R)0.70710678118654752440;
+  cpx<R> a[4][4];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    cpx<R> q[4] = {v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]};
+    dft4<R, DIR>(q);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) a[n1][k2] = q[k2];
+  }
+  // twiddles W16^{n1 k2} = cos(2 pi n1 k2/16) + DIR i sin(2 pi n1 k2/16)
+  const R cs[10] = {(R)1, c1, h, s1, (R)0, -s1, -h, -c1, (R)-1, -c1};
+  const R sn[10] = {(R)0, s1, h, c1, (R)1, c1, h, s1, (R)0, -s1};
+#pragma unroll
+  for (int n1 = 1; n1 < 4; ++n1) {
+#pragma unroll
+    for (int k2 = 1; k2 < 4; ++k2) {
+      const int m = n1 * k2;  // 1..9
+      cpx<R> w{cs[m], (R)DIR * sn[m]};
+      a[n1][k2] = cmul(a[n1][k2], w);
+    }
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    cpx<R> q[4] = {a[0][k2], a[1][k2], a[2][k2], a[3][k2]};
+    dft4<R, DIR>(q);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) v[k2 + 4 * k1] = q[k1];
+  }
+}
+
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ void dft(cpx<R>* v) {
+  if constexpr (RAD == 2) dft2<R, DIR>(v);
+  else if constexpr (RAD == 3) dft3<R, DIR>(v);
+  else if constexpr (RAD == 4) dft4<R, DIR>(v);
+  else if constexpr (RAD == 8) dft8<R, DIR>(v);
+  else if constexpr (RAD == 16) dft16<R, DIR>(v);
+  else static_assert(RAD == 2, "unsupported radix");
+}
+
+// One Stockham stage on the thread's part of one transform held in LDS.
+// tw[k] = exp(-2 pi i k / L) for k in [0, L).
+template <typename R, int L, int DIR, int S>
+__device__ __forceinline__ void fft_stage(cpx<R>* __restrict__ buf, int t,
+                                          const cpx<R>* __restrict__ tw) {
+  using P = FftPlan<L>;
+  constexpr int RAD = P::R[S];
+  constexpr int Ns = StageNs<L, S>::value;
+  constexpr int T = P::T, E = P::E, NB = E / RAD, LR = L / RAD;
+  static_assert(E % RAD == 0, "radix must divide the per-thread element count");
+  cpx<R> v[E];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + b * T;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[b * RAD + r] = buf[j + r * LR];
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + b * T;
+    if constexpr (Ns > 1) {
+      const int k = j % Ns;
+      constexpr int step = L / (Ns * RAD);
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        cpx<R> w = tw[r * k * step];
+        if (DIR > 0) w.y = -w.y;
+        v[b * RAD + r] = cmul(v[b * RAD + r], w);
+      }
+    }
+    dft<R, RAD, DIR>(&v[b * RAD]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + b * T;
+    const int k = j % Ns;
+    const int base = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) buf[base + r * Ns] = v[b * RAD + r];
+  }
+  __syncthreads();
+}
+
+template <typename R, int L, int DIR, int S>
+__device__ __forceinline__ void fft_stages(cpx<R>* buf, int t, const cpx<R>* tw) {
+  if constexpr (S < FftPlan<L>::NS) {
+    fft_stage<R, L, DIR, S>(buf, t, tw);
+    fft_stages<R, L, DIR, S + 1>(buf, t, tw);
+  }
+}
+
+// Full transform of the length-L sequence in `buf` (all threads of the
+// workgroup must call it together: it contains barriers).
+template <typename R, int L, int DIR>
+__device__ __forceinline__ void fft_lds(cpx<R>* buf, int t, const cpx<R>* tw) {
+  fft_stages<R, L, DIR, 0>(buf, t, tw);
+}

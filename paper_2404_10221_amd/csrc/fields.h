@@ -1,0 +1,40 @@
+// Device evaluation of the analytic e, f, psi families used as synthetic
+// workloads, the compact right-hand side operator F = (prod_l H_{alpha_l}) f
+// (eq. eq2.2, Appendix A), and small utility kernels.
+#pragma once
+#include "common.h"
+
+#define RSFDE_MAXMODES 8
+#define RSFDE_MC_STRIDE 32  // per-axis manufactured-source coefficients
+
+struct FieldDev {
+  int kind;
+  int K;                     // sine modes per axis
+  int a;                     // manufactured exponent
+  int pad;
+  double c[4];
+  double norm;               // sum |amp| (SINE_FIELD)
+  const double* amp;         // K^d amplitudes, k_1 fastest
+  const double* sintab[3];   // sin((k+1) pi x_{i,j}) at [k*(N_i+2) + j], closure index j
+  const double* mc;          // manufactured: per axis [left(13), right(13), sigma] at axis*32
+};
+
+struct GridDev {
+  int d;
+  int closure;               // 1: closure grid (N_i+2 points), 0: interior
+  int N[3];                  // interior sizes
+  double lo[3], h[3];
+  double kappa[3];
+  int64_t size;
+};
+
+hipError_t fields_eval(const FieldDev& e, const FieldDev& f, int which, const GridDev& g, double t,
+                       double* out, hipStream_t s);
+hipError_t fields_sintab(int K, int Ncl, double lo, double h, double* tab, hipStream_t s);
+hipError_t compute_F(const double* fcl, const GridDev& interior, const double* alpha, double* F,
+                     hipStream_t s);
+hipError_t minmax_reset(double* mm, hipStream_t s);
+hipError_t minmax_accum(const double* e, int64_t n, double* mm, double* partial, unsigned* counter,
+                        hipStream_t s);
+hipError_t convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
+hipError_t fill_f64(double* x, int64_t n, double v, hipStream_t s);

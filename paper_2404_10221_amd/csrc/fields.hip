@@ -1,0 +1,290 @@
+// Field evaluation kernels (synthetic workloads) and the compact source operator.
+#include <math.h>
+
+#include "fields.h"
+#include "rsfde.h"
+
+__device__ __forceinline__ double sine_modes(const FieldDev& F, int d, const int* jc, const int* Ncl) {
+  const int K = F.K;
+  double acc = 0.0;
+  if (d == 1) {
+    for (int k1 = 0; k1 < K; ++k1) acc += F.amp[k1] * F.sintab[0][k1 * Ncl[0] + jc[0]];
+  } else if (d == 2) {
+    for (int k2 = 0; k2 < K; ++k2) {
+      const double s2 = F.sintab[1][k2 * Ncl[1] + jc[1]];
+      double inner = 0.0;
+      for (int k1 = 0; k1 < K; ++k1) inner += F.amp[k1 + K * k2] * F.sintab[0][k1 * Ncl[0] + jc[0]];
+      acc += inner * s2;
+    }
+  } else {
+    for (int k3 = 0; k3 < K; ++k3) {
+      const double s3 = F.sintab[2][k3 * Ncl[2] + jc[2]];
+      for (int k2 = 0; k2 < K; ++k2) {
+        const double s23 = s3 * F.sintab[1][k2 * Ncl[1] + jc[1]];
+        double inner = 0.0;
+        for (int k1 = 0; k1 < K; ++k1)
+          inner += F.amp[k1 + K * (k2 + K * k3)] * F.sintab[0][k1 * Ncl[0] + jc[0]];
+        acc += inner * s23;
+      }
+    }
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double e_value(const FieldDev& E, int d, const double* x, const int* jc,
+                                          const int* Ncl, double t) {
+  switch (E.kind) {
+    case RSFDE_FIELD_CONST:
+      return E.c[0];
+    case RSFDE_FIELD_SUMSQ_EXP: {
+      double s = 0.0;
+      for (int i = 0; i < d; ++i) s += x[i] * x[i];
+      return (s + exp(-t)) / E.c[0];
+    }
+    case RSFDE_FIELD_POLY_T: {
+      double p = 1.0;
+      for (int i = 0; i < d; ++i) p *= pow(x[i], E.c[3]);
+      return E.c[0] + E.c[1] * (1.0 + E.c[2] * t) * p;
+    }
+    case RSFDE_FIELD_SINPROD_COS: {
+      double p = 1.0;
+      for (int i = 0; i < d; ++i) p *= sinpi(x[i]);
+      return E.c[0] + E.c[1] * p * cos(t);
+    }
+    case RSFDE_FIELD_SINE_FIELD: {
+      const double g = sine_modes(E, d, jc, Ncl);
+      return E.c[0] + E.c[1] * 0.5 * (1.0 + g / E.norm);
+    }
+    default:
+      return 0.0;
+  }
+}
+
+__device__ __forceinline__ double poly_p(double x, int a) {
+  const double b = x * (1.0 - x);
+  double p = 1.0;
+  for (int i = 0; i < a; ++i) p *= b;
+  return p;
+}
+
+// Riesz derivative of x^a (1-x)^a from the Riemann-Liouville power rule; the
+// coefficients (times the Gamma ratios) come from the host.
+__device__ __forceinline__ double riesz_poly(const double* mc, double alpha, int a, double x) {
+  double acc = 0.0;
+  for (int k = 0; k <= 2 * a; ++k) {
+    const double cl = mc[k], cr = mc[13 + k];
+    if (cl != 0.0) acc += cl * pow(x, (double)k - alpha);
+    if (cr != 0.0) acc += cr * pow(1.0 - x, (double)k - alpha);
+  }
+  return mc[26] * acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_fields_eval(const FieldDev E, const FieldDev F, int which, const GridDev g, double t,
+              double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.size) return;
+  const int d = g.d;
+  int jc[3] = {0, 0, 0};
+  int Ncl[3] = {1, 1, 1};
+  double x[3] = {0.0, 0.0, 0.0};
+  int64_t r = idx;
+  for (int i = 0; i < d; ++i) {
+    const int ni = g.closure ? g.N[i] + 2 : g.N[i];
+    const int64_t ji = r % ni;
+    r /= ni;
+    jc[i] = (int)ji + (g.closure ? 0 : 1);
+    Ncl[i] = g.N[i] + 2;
+    x[i] = g.lo[i] + (double)jc[i] * g.h[i];
+  }
+  double v = 0.0;
+  if (which == RSFDE_WHICH_E) {
+    v = e_value(E, d, x, jc, Ncl, t);
+  } else if (which == RSFDE_WHICH_F) {
+    if (F.kind == RSFDE_FIELD_SINE_MODES) {
+      v = sine_modes(F, d, jc, Ncl);
+    } else if (F.kind == RSFDE_FIELD_MANUFACTURED) {
+      const double A = F.c[0] * exp(-t);
+      double pr[3];
+      double u = A;
+      for (int i = 0; i < d; ++i) {
+        pr[i] = poly_p(x[i], F.a);
+        u *= pr[i];
+      }
+      const double ev = e_value(E, d, x, jc, Ncl, t);
+      v = -ev * u;  // e u_t, u_t = -u
+      for (int i = 0; i < d; ++i) {
+        double other = A;
+        for (int l = 0; l < d; ++l)
+          if (l != i) other *= pr[l];
+        v -= g.kappa[i] * other * riesz_poly(F.mc + i * RSFDE_MC_STRIDE, F.mc[i * RSFDE_MC_STRIDE + 27], F.a, x[i]);
+      }
+    }
+  } else {
+    if (F.kind == RSFDE_FIELD_MANUFACTURED) {
+      double u = F.c[0];
+      for (int i = 0; i < d; ++i) u *= poly_p(x[i], F.a);
+      v = u;
+    }
+  }
+  out[idx] = v;
+}
+
+hipError_t fields_eval(const FieldDev& e, const FieldDev& f, int which, const GridDev& g, double t,
+                       double* out, hipStream_t s) {
+  if (g.size == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fields_eval, dim3((unsigned)((g.size + 255) / 256)), dim3(256), 0, s, e, f,
+                     which, g, t, out);
+  return hipGetLastError();
+}
+
+__global__ void k_sintab(int K, int Ncl, double lo, double h, double* tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K * Ncl) return;
+  const int k = i / Ncl, j = i - k * Ncl;
+  tab[i] = sinpi((double)(k + 1) * (lo + (double)j * h));
+}
+
+hipError_t fields_sintab(int K, int Ncl, double lo, double h, double* tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_sintab, dim3((K * Ncl + 255) / 256), dim3(256), 0, s, K, Ncl, lo, h, tab);
+  return hipGetLastError();
+}
+
+// F_J = sum over the 3^d neighbours of prod_i w_i(a_i) f_{J+a} on the closure
+// grid, w(0) = 1 - alpha_i/12, w(+-1) = alpha_i/24 (every interior index lies
+// inside the stencil's support, so H acts as the stencil on each axis).
+__global__ void __launch_bounds__(256)
+k_compute_F(const double* __restrict__ fcl, const GridDev g, double a0, double a1, double a2,
+            double* __restrict__ F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.size) return;
+  const int d = g.d;
+  const double al[3] = {a0, a1, a2};
+  int j[3] = {0, 0, 0};
+  int64_t sc[3] = {0, 0, 0};
+  int64_t r = idx, stride = 1;
+  for (int i = 0; i < d; ++i) {
+    j[i] = (int)(r % g.N[i]) + 1;
+    r /= g.N[i];
+    sc[i] = stride;
+    stride *= (g.N[i] + 2);
+  }
+  int64_t c0 = 0;
+  for (int i = 0; i < d; ++i) c0 += (int64_t)j[i] * sc[i];
+  double w[3][3];
+  for (int i = 0; i < 3; ++i) {
+    const double a = i < d ? al[i] : 0.0;
+    w[i][0] = a / 24.0;
+    w[i][1] = i < d ? 1.0 - a / 12.0 : 1.0;
+    w[i][2] = a / 24.0;
+  }
+  double acc = 0.0;
+  const int n2 = d >= 2 ? 3 : 1, n3 = d >= 3 ? 3 : 1;
+  for (int c = 0; c < n3; ++c) {
+    for (int b = 0; b < n2; ++b) {
+      const double wbc = (d >= 3 ? w[2][c] : 1.0) * (d >= 2 ? w[1][b] : 1.0);
+      const int64_t off = c0 + (d >= 3 ? (int64_t)(c - 1) * sc[2] : 0) + (d >= 2 ? (int64_t)(b - 1) * sc[1] : 0);
+      acc += wbc * (w[0][0] * fcl[off - 1] + w[0][1] * fcl[off] + w[0][2] * fcl[off + 1]);
+    }
+  }
+  F[idx] = acc;
+}
+
+hipError_t compute_F(const double* fcl, const GridDev& g, const double* alpha, double* F,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_compute_F, dim3((unsigned)((g.size + 255) / 256)), dim3(256), 0, s, fcl, g,
+                     alpha[0], alpha[1], alpha[2], F);
+  return hipGetLastError();
+}
+
+__global__ void k_minmax_reset(double* mm) {
+  mm[0] = INFINITY;
+  mm[1] = -INFINITY;
+}
+
+hipError_t minmax_reset(double* mm, hipStream_t s) {
+  hipLaunchKernelGGL(k_minmax_reset, dim3(1), dim3(1), 0, s, mm);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+k_minmax(const double* __restrict__ e, int64_t n, double* mm, double* partial, unsigned* counter) {
+  double lo = INFINITY, hi = -INFINITY;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = e[i];
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  __shared__ double sl[4], sh[4];
+  __shared__ int amlast;
+  if ((threadIdx.x & 63) == 0) {
+    sl[threadIdx.x >> 6] = lo;
+    sh[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = fmin(lo, sl[w]);
+      hi = fmax(hi, sh[w]);
+    }
+    partial[2 * blockIdx.x] = lo;
+    partial[2 * blockIdx.x + 1] = hi;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) amlast = atomicAdd(counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!amlast) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    double L = mm[0], H = mm[1];
+    for (unsigned b = 0; b < gridDim.x; ++b) {
+      L = fmin(L, partial[2 * b]);
+      H = fmax(H, partial[2 * b + 1]);
+    }
+    mm[0] = L;
+    mm[1] = H;
+    *counter = 0u;
+  }
+}
+
+hipError_t minmax_accum(const double* e, int64_t n, double* mm, double* partial, unsigned* counter,
+                        hipStream_t s) {
+  int64_t b = (n + 2047) / 2048;
+  if (b > 512) b = 512;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_minmax, dim3((unsigned)b), dim3(256), 0, s, e, n, mm, partial, counter);
+  return hipGetLastError();
+}
+
+__global__ void k_f64_f32(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (float)in[i];
+}
+
+hipError_t convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  int64_t b = (n + 1023) / 1024;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_f64_f32, dim3((unsigned)b), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
+hipError_t fill_f64(double* x, int64_t n, double v, hipStream_t s) {
+  int64_t b = (n + 1023) / 1024;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)b), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}

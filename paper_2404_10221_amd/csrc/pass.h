@@ -1,0 +1,469 @@
+// Pencil pass kernels: one sweep over the grid along one axis that applies,
+// per pencil and inside LDS, a fused combination of
+//   * the B_{alpha_i} tridiagonal stencil (eq. Ha),
+//   * the Toeplitz factor S_{alpha_i} (eq. eq0) by circulant embedding of length
+//     L = 2(N_i+1): zero-pad, FFT, multiply by the real circulant spectrum,
+//     inverse FFT, keep the first N_i entries,
+//   * the type-I sine transform (Section 3, eq. diag) through the FFT of the odd
+//     extension [0, x_1..x_N, 0, -x_N..-x_1] of length L,
+//   * the diagonal 1/mu_K scaling of the tau preconditioner in the sine basis.
+// Two real pencils are packed as the real and imaginary parts of one complex
+// transform.  Operators along different axes commute, so the d-dimensional
+// matvec A v = B_alpha E v + S_alpha v and the preconditioner solve are chains of
+// such passes (one sweep per axis and per transform direction).
+#pragma once
+#include "common.h"
+#include "fft.h"
+
+enum : int { OP_MV_FIRST = 0, OP_MV_MID = 1, OP_MV_LAST = 2, OP_DST = 3, OP_DSD = 4 };
+enum : int {
+  FL_DST_AFTER = 1,      // MV_LAST: follow by a sine transform along the same axis
+  FL_PREC_FULL = 2,      // MV_LAST (d = 1): follow by transform, 1/mu scaling, transform
+  FL_IN64 = 4,           // in_c holds FP64 values (else the pass precision)
+  FL_OUT64 = 8,          // out_a receives FP64 values (else the pass precision)
+  FL_FIRST_IS_LAST = 16  // MV_LAST of a one-axis problem: stencil input is e .* v
+};
+
+struct PassArgs {
+  int op, flags;
+  int N;                 // pencil length along the pass axis
+  int d, axis;
+  int64_t inner;         // element stride of the pass axis (prod of N_l, l < axis)
+  int64_t npencil;       // pencils in the pass (= n / N)
+  int64_t tiles_inner;   // strided passes: tiles across the inner index range
+  int64_t ntiles;        // workgroups launched
+  const void* in_c;      // Toeplitz / transform input (v for the first pass)
+  const void* in_a;      // stencil input (e for the first pass)
+  const double* in_x;    // MV_LAST: additive FP64 vector (b or F), may be NULL
+  const double* sc_ptr;  // device scalar multiplying in_c, may be NULL
+  void* out_a;           // a_i, w, or the transformed vector
+  void* out_c;           // c_i = B_i c_{i-1} (MV_FIRST / MV_MID)
+  double bd, bo;         // B stencil: 1 - alpha/12 and alpha/24
+  double eta;            // signed eta_i of the Toeplitz term
+  double gam;            // MV_LAST: multiplier of the operator part
+  double xcoef;          // MV_LAST: multiplier of in_x
+  const void* chat;      // circulant spectrum divided by L (precision R), length L
+  const void* tw;        // exp(-2 pi i k/L), k < L (cpx<R>)
+  int Nax[3];            // grid sizes per axis (for the mode indices of mu)
+  const void* lam[3];    // B eigenvalues per axis (precision R), sine mode k+1 at [k]
+  const void* wq[3];     // eta_i q_i / lambda_i per axis (precision R)
+  const double* ebar;    // device scalar ebar
+  double pscale;         // prod_i 1/L_i: normalisation of the two sine transforms
+};
+
+template <typename R>
+__device__ __forceinline__ R ld_any(const void* p, int64_t i, bool is64) {
+  if constexpr (sizeof(R) == 8) {
+    return ((const double*)p)[i];
+  } else {
+    return is64 ? (R)((const double*)p)[i] : ((const R*)p)[i];
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void st_any(void* p, int64_t i, R v, bool is64) {
+  if constexpr (sizeof(R) == 8) {
+    ((double*)p)[i] = v;
+  } else {
+    if (is64) ((double*)p)[i] = (double)v;
+    else ((R*)p)[i] = v;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R comp_of(cpx<R> z, int c) { return c ? z.y : z.x; }
+
+template <typename R>
+__device__ __forceinline__ void set_comp(cpx<R>& z, int c, R v) {
+  if (c) z.y = v; else z.x = v;
+}
+
+// Pencils packed per workgroup: F complex transforms, i.e. 2F real pencils.
+template <typename R, int L, bool STRIDED>
+struct PassShape {
+  static constexpr int T = FftPlan<L>::T;
+  static constexpr int bytes_per_fft = (L + 1) * (int)sizeof(cpx<R>);
+  static constexpr int cap = STRIDED ? 160 * 1024 : 80 * 1024;
+  static constexpr int want = STRIDED ? (512 / T > 4 ? 512 / T : 4) : (256 / T > 1 ? 256 / T : 1);
+  static constexpr int lim = cap / bytes_per_fft;
+  static constexpr int F0 = want < lim ? want : lim;
+  static constexpr int F1 = F0 * T > 1024 ? 1024 / T : F0;
+  static constexpr int F = F1 < 1 ? 1 : F1;
+  static constexpr int NT = F * T;
+};
+
+template <typename R, int L, int F, bool STRIDED>
+__global__ void __launch_bounds__(F * FftPlan<L>::T)
+rsfde_pass_kernel(const PassArgs a) {
+  using P = FftPlan<L>;
+  constexpr int T = P::T, E = P::E, NT = F * T, LP = L + 1, PT = 2 * F;
+  constexpr int NE = STRIDED ? E : E / 2;  // element slots per thread
+  __shared__ cpx<R> lds[F * LP];
+
+  const cpx<R>* __restrict__ tw = (const cpx<R>*)a.tw;
+  const int tid = threadIdx.x;
+  const int f = tid / T;
+  const int t = tid - f * T;
+  cpx<R>* buf = lds + f * LP;
+  const int N = a.N;
+  const bool in64 = (a.flags & FL_IN64) != 0;
+  const bool out64 = (a.flags & FL_OUT64) != 0;
+
+  // ---- tile geometry
+  const int64_t tile = blockIdx.x;
+  int64_t row0 = 0, gbase = 0;
+  int nvalid;
+  if constexpr (!STRIDED) {
+    row0 = tile * PT;
+    const int64_t rem = a.npencil - row0;
+    nvalid = rem < PT ? (int)rem : PT;
+  } else {
+    const int64_t o = tile / a.tiles_inner;
+    const int64_t pin0 = (tile - o * a.tiles_inner) * PT;
+    const int64_t rem = a.inner - pin0;
+    nvalid = rem < PT ? (int)rem : PT;
+    gbase = o * (int64_t)N * a.inner + pin0;
+  }
+  const int64_t inner = a.inner;
+
+  // element (slot i) -> position p, pencil-in-tile pp (strided) ; validity
+  auto s_pos = [&](int i, int& p, int& pp) {
+    const int flat = tid + i * NT;
+    p = flat / PT;
+    pp = flat - p * PT;
+  };
+  auto c_row = [&](int comp) -> int64_t { return row0 + 2 * f + comp; };
+
+  R sc = (R)1;
+  if (a.sc_ptr) sc = (R)(*a.sc_ptr);
+  const R bd = (R)a.bd, bo = (R)a.bo, eta = (R)a.eta;
+  const R* __restrict__ chat = (const R*)a.chat;
+
+  cpx<R> ra[STRIDED ? 1 : NE];  // contiguous: packed pair per slot
+  R rs[STRIDED ? NE : 1];       // strided: one value per slot
+  (void)ra;
+  (void)rs;
+
+  const int op = a.op;
+  const bool is_mv = op <= OP_MV_LAST;
+  bool dst_phase = !is_mv;          // a sine transform follows
+  bool scale_phase = op == OP_DSD;  // and a 1/mu scaling + second transform
+
+  if (is_mv) {
+    const bool ev_mode = op == OP_MV_FIRST || (a.flags & FL_FIRST_IS_LAST);
+    // ---- load: Toeplitz input c into slots [0,N), stencil input into [N+1, 2N+1)
+    if (t == 0) {
+      buf[N] = cpx<R>{0, 0};
+      buf[2 * N + 1] = cpx<R>{0, 0};
+    }
+    if constexpr (!STRIDED) {
+      const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+      const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = t + i * T;
+        if (p < N) {
+          R c0 = v0 ? ld_any<R>(a.in_c, b0 + p, in64) * sc : (R)0;
+          R c1 = v1 ? ld_any<R>(a.in_c, b1 + p, in64) * sc : (R)0;
+          R a0 = v0 ? ld_any<R>(a.in_a, b0 + p, false) : (R)0;
+          R a1 = v1 ? ld_any<R>(a.in_a, b1 + p, false) : (R)0;
+          if (ev_mode) {
+            a0 *= c0;
+            a1 *= c1;
+          }
+          buf[p] = cpx<R>{c0, c1};
+          buf[N + 1 + p] = cpx<R>{a0, a1};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        int p, pp;
+        s_pos(i, p, pp);
+        if (p < N) {
+          const bool v = pp < nvalid;
+          const int64_t g = gbase + (int64_t)p * inner + pp;
+          R c = v ? ld_any<R>(a.in_c, g, in64) * sc : (R)0;
+          R av = v ? ld_any<R>(a.in_a, g, false) : (R)0;
+          if (ev_mode) av *= c;
+          cpx<R>* bb = lds + (pp >> 1) * LP;
+          set_comp(bb[p], pp & 1, c);
+          set_comp(bb[N + 1 + p], pp & 1, av);
+        }
+      }
+    }
+    __syncthreads();
+    // ---- stencils: keep B a in registers, store c_out = B c
+    const bool store_c = op != OP_MV_LAST;
+    if constexpr (!STRIDED) {
+      const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+      const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = t + i * T;
+        if (p < N) {
+          cpx<R> cm = p > 0 ? buf[p - 1] : cpx<R>{0, 0};
+          cpx<R> bc = buf[p] * bd + (cm + buf[p + 1]) * bo;
+          cpx<R> ba = buf[N + 1 + p] * bd + (buf[N + p] + buf[N + 2 + p]) * bo;
+          ra[i] = ba;
+          if (store_c) {
+            if (v0) st_any<R>(a.out_c, b0 + p, bc.x, false);
+            if (v1) st_any<R>(a.out_c, b1 + p, bc.y, false);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        int p, pp;
+        s_pos(i, p, pp);
+        if (p < N) {
+          const int c = pp & 1;
+          const cpx<R>* bb = lds + (pp >> 1) * LP;
+          R cm = p > 0 ? comp_of(bb[p - 1], c) : (R)0;
+          R bc = comp_of(bb[p], c) * bd + (cm + comp_of(bb[p + 1], c)) * bo;
+          R ba = comp_of(bb[N + 1 + p], c) * bd + (comp_of(bb[N + p], c) + comp_of(bb[N + 2 + p], c)) * bo;
+          rs[i] = ba;
+          if (store_c && pp < nvalid) st_any<R>(a.out_c, gbase + (int64_t)p * inner + pp, bc, false);
+        }
+      }
+    }
+    __syncthreads();
+    for (int k = N + t; k < L; k += T) buf[k] = cpx<R>{0, 0};
+    __syncthreads();
+    // ---- Toeplitz product by circulant embedding
+    fft_lds<R, L, -1>(buf, t, tw);
+    for (int k = t; k < L; k += T) buf[k] = buf[k] * chat[k];
+    __syncthreads();
+    fft_lds<R, L, +1>(buf, t, tw);
+    // ---- combine
+    const bool last = op == OP_MV_LAST;
+    const bool want_dst = last && (a.flags & (FL_DST_AFTER | FL_PREC_FULL));
+    const R gam = (R)a.gam, xcoef = (R)a.xcoef;
+    const double* __restrict__ xin = a.in_x;
+    if constexpr (!STRIDED) {
+      const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+      const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = t + i * T;
+        if (p < N) {
+          cpx<R> w = ra[i] + buf[p] * eta;
+          if (last) {
+            w = w * gam;
+            if (xin) {
+              R x0 = v0 ? (R)xin[b0 + p] : (R)0;
+              R x1 = v1 ? (R)xin[b1 + p] : (R)0;
+              w = w + cpx<R>{x0, x1} * xcoef;
+            }
+          }
+          if (want_dst) {
+            ra[i] = w;
+          } else {
+            if (v0) st_any<R>(a.out_a, b0 + p, w.x, out64 && last);
+            if (v1) st_any<R>(a.out_a, b1 + p, w.y, out64 && last);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        int p, pp;
+        s_pos(i, p, pp);
+        if (p < N) {
+          const int c = pp & 1;
+          const cpx<R>* bb = lds + (pp >> 1) * LP;
+          const int64_t g = gbase + (int64_t)p * inner + pp;
+          const bool v = pp < nvalid;
+          R w = rs[i] + comp_of(bb[p], c) * eta;
+          if (last) {
+            w = w * gam;
+            if (xin && v) w += (R)xin[g] * xcoef;
+          }
+          if (want_dst) {
+            rs[i] = w;
+          } else if (v) {
+            st_any<R>(a.out_a, g, w, out64 && last);
+          }
+        }
+      }
+    }
+    if (!want_dst) return;  // uniform across the workgroup
+    dst_phase = true;
+    scale_phase = (a.flags & FL_PREC_FULL) != 0;
+    __syncthreads();
+    // ---- odd extension of w for the sine transform
+    if (t == 0) {
+      buf[0] = cpx<R>{0, 0};
+      buf[N + 1] = cpx<R>{0, 0};
+    }
+    if constexpr (!STRIDED) {
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = t + i * T;
+        if (p < N) {
+          buf[p + 1] = ra[i];
+          buf[L - 1 - p] = -ra[i];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        int p, pp;
+        s_pos(i, p, pp);
+        if (p < N) {
+          cpx<R>* bb = lds + (pp >> 1) * LP;
+          set_comp(bb[p + 1], pp & 1, rs[i]);
+          set_comp(bb[L - 1 - p], pp & 1, -rs[i]);
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+    // ---- OP_DST / OP_DSD: load the odd extension of the input
+    if (t == 0) {
+      buf[0] = cpx<R>{0, 0};
+      buf[N + 1] = cpx<R>{0, 0};
+    }
+    if constexpr (!STRIDED) {
+      const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+      const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = t + i * T;
+        if (p < N) {
+          R x0 = v0 ? ld_any<R>(a.in_c, b0 + p, in64) : (R)0;
+          R x1 = v1 ? ld_any<R>(a.in_c, b1 + p, in64) : (R)0;
+          cpx<R> z{x0, x1};
+          buf[p + 1] = z;
+          buf[L - 1 - p] = -z;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        int p, pp;
+        s_pos(i, p, pp);
+        if (p < N) {
+          const bool v = pp < nvalid;
+          R x = v ? ld_any<R>(a.in_c, gbase + (int64_t)p * inner + pp, in64) : (R)0;
+          cpx<R>* bb = lds + (pp >> 1) * LP;
+          set_comp(bb[p + 1], pp & 1, x);
+          set_comp(bb[L - 1 - p], pp & 1, -x);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- sine transform(s): FFT of the odd extension; for z = x0 + i x1 the
+  // transforms are 2 DST(x0) = -Im Z_k, 2 DST(x1) = Re Z_k (k = 1..N).
+  (void)dst_phase;
+  fft_lds<R, L, -1>(buf, t, tw);
+  if (scale_phase) {
+    // 1/mu_K in the sine basis (eq. Pa, Lemma le:eig, Lemma Heig, eq. q); the
+    // pass runs along axis 0, the other axes are already transformed.
+    const R* lam0 = (const R*)a.lam[0];
+    const R* wq0 = (const R*)a.wq[0];
+    const R eb = (R)(*a.ebar);
+    const R ps = (R)a.pscale;
+    R Lam[2] = {(R)1, (R)1}, Sig[2] = {(R)0, (R)0};
+    if constexpr (!STRIDED) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        int64_t rr = c_row(c);
+        if (rr >= a.npencil) rr = 0;
+        for (int l = 1; l < a.d; ++l) {
+          const int64_t k = rr % a.Nax[l];
+          rr /= a.Nax[l];
+          Lam[c] *= ((const R*)a.lam[l])[k];
+          Sig[c] += ((const R*)a.wq[l])[k];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = t + i * T;
+        if (p < N) {
+          const cpx<R> Z = buf[p + 1];
+          const R l0 = lam0[p], w0 = wq0[p];
+          const R s0 = ps / (Lam[0] * l0 * (eb + w0 + Sig[0]));
+          const R s1 = ps / (Lam[1] * l0 * (eb + w0 + Sig[1]));
+          ra[i] = cpx<R>{-Z.y * s0, Z.x * s1};
+        }
+      }
+      __syncthreads();
+      if (t == 0) {
+        buf[0] = cpx<R>{0, 0};
+        buf[N + 1] = cpx<R>{0, 0};
+      }
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = t + i * T;
+        if (p < N) {
+          buf[p + 1] = ra[i];
+          buf[L - 1 - p] = -ra[i];
+        }
+      }
+      __syncthreads();
+      fft_lds<R, L, -1>(buf, t, tw);
+    }
+    // (the host only requests the scaling on the contiguous axis)
+  }
+  // ---- store the transformed pencils
+  if constexpr (!STRIDED) {
+    const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+    const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int p = t + i * T;
+      if (p < N) {
+        const cpx<R> Z = buf[p + 1];
+        if (v0) st_any<R>(a.out_a, b0 + p, -Z.y, out64);
+        if (v1) st_any<R>(a.out_a, b1 + p, Z.x, out64);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      int p, pp;
+      s_pos(i, p, pp);
+      if (p < N && pp < nvalid) {
+        const cpx<R>* bb = lds + (pp >> 1) * LP;
+        const cpx<R> Z = bb[p + 1];
+        st_any<R>(a.out_a, gbase + (int64_t)p * inner + pp, (pp & 1) ? Z.x : -Z.y, out64);
+      }
+    }
+  }
+}
+
+// Host launcher for one (precision, length); defined in the per-length
+// instantiation units.  Returns a hipError_t.
+template <typename R, int L>
+hipError_t launch_pass_L(const PassArgs& a, bool strided, hipStream_t s);
+
+// Workgroup shape the launcher uses (threads, pencils per tile).
+template <typename R, int L>
+inline void pass_shape(bool strided, int* nt, int* pencils_per_tile) {
+  if (strided) {
+    *nt = PassShape<R, L, true>::NT;
+    *pencils_per_tile = 2 * PassShape<R, L, true>::F;
+  } else {
+    *nt = PassShape<R, L, false>::NT;
+    *pencils_per_tile = 2 * PassShape<R, L, false>::F;
+  }
+}
+
+#define RSFDE_INSTANTIATE_PASS(R, L)                                                   \
+  template <>                                                                          \
+  hipError_t launch_pass_L<R, L>(const PassArgs& a, bool strided, hipStream_t s) {     \
+    if (strided) {                                                                     \
+      using S = PassShape<R, L, true>;                                                 \
+      hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, true>), dim3((unsigned)a.ntiles), \
+                         dim3(S::NT), 0, s, a);                                        \
+    } else {                                                                           \
+      using S = PassShape<R, L, false>;                                                \
+      hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, false>), dim3((unsigned)a.ntiles), \
+                         dim3(S::NT), 0, s, a);                                        \
+    }                                                                                  \
+    return hipGetLastError();                                                          \
+  }
