@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the tau-preconditioned GMRES time stepper on one MI355X.
+
+A step is one Crank-Nicolson time step of the 2-D workload (N = 1023 per axis,
+alpha = (1.3, 1.7), kappa = (1, 0.5), e = 2 + sin(pi x) sin(pi y) cos t, f = 8x8
+sine modes with seeded N(0,1) amplitudes, psi = 0, dt = 1/32, GMRES(30) to
+rtol 1e-10, FP64): evaluate e at t_{m+1/2}, form the right-hand side and run
+the preconditioned GMRES solve on the device.  Inputs are resident in HBM before
+the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-steps/sec (PGMRES to 1e-10) on 2D 1023²; HBM GB/s of FFT/DST kernels"
+HBM_PEAK_GBS = 8000.0
+KCLASS_NAMES = ("mv_first", "mv_mid", "mv_last", "dst", "dsd", "dots", "orth_dots", "orth_norm", "update")
+KCLASS_KERNELS = {
+    "mv_first": "rsfde_pass_kernel<double, 2048, 1, false> (first-axis operator pass)",
+    "mv_last": "rsfde_pass_kernel<double, 2048, 4, true> (last-axis operator pass + sine transform)",
+    "dst": "rsfde_pass_kernel<double, 2048, 4, true> (sine-transform pass)",
+    "dsd": "rsfde_pass_kernel<double, 2048, 1, false> (transform, 1/mu scaling, transform)",
+    "dots": "k_dots (CGS2 sweep 1)",
+    "orth_dots": "k_orth_dots (CGS2 sweep 2)",
+    "orth_norm": "k_orth_norm_givens (CGS2 sweep 3 + Givens)",
+    "update": "k_update",
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2404_10221_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kclass: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    ent = data.get("kernels", {}).get(kclass)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+class Stepper:
+    """Owns a handle on one instance and steps it with device-evaluated fields."""
+
+    def __init__(self, inst, **over):
+        import torch
+        from paper_2404_10221_amd import rsfde as R
+        self.R = R
+        self.inst = inst
+        self.S = R.Solver([R.params_from_instance(inst, **over)])
+        R.rsfde_set_fields(self.S.h, 0, inst.e, inst.f, inst.psi)
+        R.rsfde_prescan_ebar(self.S.h, 0, inst.M)
+        self.u = torch.empty(inst.size, dtype=torch.float64, device="cuda")
+        self.e = torch.empty(inst.size, dtype=torch.float64, device="cuda")
+        ncl = 1
+        for v in inst.n:
+            ncl *= v + 2
+        self.f = torch.empty(ncl, dtype=torch.float64, device="cuda")
+        R.rsfde_eval_field(self.S.h, 0, R.WHICH_PSI, 0.0, self.u)
+        self.f_time_dep = inst.f.time_dependent
+        R.rsfde_eval_field(self.S.h, 0, R.WHICH_F, 0.5 * inst.dt, self.f)
+        self.m = 0
+        self.iters = 0
+        self.status = 0
+
+    def step(self):
+        R = self.R
+        th = (self.m + 0.5) * self.inst.dt
+        R.rsfde_eval_field(self.S.h, 0, R.WHICH_E, th, self.e)
+        if self.f_time_dep:
+            R.rsfde_eval_field(self.S.h, 0, R.WHICH_F, th, self.f)
+        s, st = R.rsfde_step(self.S.h, self.m * self.inst.dt, [self.e], [self.f], [self.u])
+        self.status = max(self.status, s)
+        self.iters += st[0]["iters"]
+        self.m += 1
+
+    def close(self):
+        self.S.close()
+
+
+def cpu_baseline(inst, steps: int):
+    """Time the FP64 oracle on `steps` steps from psi on the host, and the GPU on the
+    same steps for a parity figure."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    P = O.OracleProblem(inst)
+    u = P.psi()
+    t0 = time.perf_counter()
+    its = []
+    for m in range(steps):
+        u, st = P.step(u, m)
+        its.append(st["iters"])
+    dt = time.perf_counter() - t0
+    g = Stepper(inst)
+    for _ in range(steps):
+        g.step()
+    got = g.u.cpu().numpy()
+    g.close()
+    ref = u.ravel()
+    par = float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+    return {
+        "value": steps / dt, "unit": "time-steps/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"first {steps} of the {inst.M} steps from psi (dense-matrix FP64 oracle, "
+                  f"{sum(its)} GMRES iterations); {dt:.1f} s wall",
+        "parity_rel_diff_gpu_vs_oracle": par,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded design is "
+              "described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_10221_amd import rsfde as R
+    from rsfde_workloads import config
+
+    torch.cuda.set_device(0)
+    inst = config("C2")
+    K, W = args.steps, args.warmup
+
+    # ---- FP64 form: warm-up with every kernel class timed (to find the dominant one)
+    g = Stepper(inst)
+    R.rsfde_set_timing(g.S.h, (1 << len(KCLASS_NAMES)) - 1)
+    for _ in range(W):
+        g.step()
+    tot = {}
+    for c, name in enumerate(KCLASS_NAMES):
+        n, ms, by = R.rsfde_get_timing(g.S.h, c)
+        tot[name] = (n, ms, by)
+    dom = max(tot, key=lambda k: tot[k][1])
+    dom_cls = KCLASS_NAMES.index(dom)
+    # ---- timed region: time only the dominant class
+    R.rsfde_set_timing(g.S.h, 1 << dom_cls)
+    it0 = g.iters
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        g.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n, ms, by = R.rsfde_get_timing(g.S.h, dom_cls)
+    R.rsfde_set_timing(g.S.h, 0)
+    elapsed = t1 - t0
+    iters = g.iters - it0
+    u64 = g.u.clone()
+    status = g.status
+    g.close()
+    achieved = (by / n) / ((ms / n) * 1e-3) / 1e9 if n else 0.0
+    traffic = read_traffic(dom)
+    out = {
+        "metric": METRIC,
+        "value": K / elapsed,
+        "unit": "time-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "C2: 2-D N=1023x1023, alpha=(1.3,1.7), kappa=(1,0.5), "
+                               "e=2+sin(pi x)sin(pi y)cos t, f=8x8 seeded sine modes, psi=0, "
+                               "dt=1/32, GMRES(30) rtol 1e-10, FP64",
+                   "unknowns": inst.size, "gmres_iters_per_step": iters / K,
+                   "status": status},
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "kernel_symbol": KCLASS_KERNELS.get(dom, dom),
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "launches_timed": n, "avg_launch_us": 1e3 * ms / n if n else None,
+            "algorithmic_bytes_per_launch": by / n if n else None,
+        },
+        "kernel_time_share_warmup": {k: round(v[1], 4) for k, v in tot.items()},
+    }
+
+    # ---- mixed FP32 operator + FP64 refinement on the same steps
+    if not args.no_mixed:
+        gm = Stepper(inst, precision=R.RSFDE_MIXED)
+        for _ in range(W):
+            gm.step()
+        it0 = gm.iters
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            gm.step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        diff = float((gm.u - u64).abs().max() / u64.abs().max().clamp_min(1e-300))
+        out["mixed"] = {"value": K / el, "unit": "time-steps/s", "ms_per_step": 1e3 * el / K,
+                        "gmres_iters_per_step": (gm.iters - it0) / K,
+                        "rel_diff_vs_fp64_gpu": diff, "status": gm.status}
+        gm.close()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,7 +152,7 @@ int rsfde_set_ebar(rsfde_handle h, int instance, double e_min, double e_max);
 
 /* One Crank-Nicolson step for every instance: given e at t_{m+1/2} on the interior
  * and f at t_{m+1/2} on the closure grid (device pointers per instance, t_m = m dt is
- * informational), overwrite u[i] = u^{(m)} with u^{(m+1)}.  stats (host array of
+ * informational), overwrite u[i] = u^{(m)} with u^{(m+1)} (u[i] 16-byte aligned).  stats (host array of
  * `count`, may be NULL) receives per-instance counters.  Synchronises the stream
  * before returning.  Returns the worst status over the instances. */
 int rsfde_step(rsfde_handle h, double t_m, const double* const* e_half,
@@ -204,11 +204,30 @@ int rsfde_rhs(rsfde_handle h, int instance, const double* e, const double* F,
 int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* q,
                      double* lambda);
 
-/* Enable (1) or disable (0) per-kernel HIP-event timing of the transform passes;
- * rsfde_get_timing returns the number of timed pass launches, their summed
- * milliseconds and summed algorithmic HBM bytes since the last enable. */
-int rsfde_set_timing(rsfde_handle h, int enable);
-int rsfde_get_timing(rsfde_handle h, long long* launches, double* ms, double* bytes);
+/* Evaluate the registered e field of one instance at the M midpoints
+ * t_{m+1/2} = (m + 1/2) dt and set ebar from its extremes (eq. dhat, eq. bard).
+ * Time-independent fields are sampled once. */
+int rsfde_prescan_ebar(rsfde_handle h, int instance, int M);
+
+/* Kernel classes for HIP-event timing (bit i of the mask enables class i). */
+#define RSFDE_K_MV_FIRST    0  /* first-axis operator pass */
+#define RSFDE_K_MV_MID      1  /* middle-axis operator pass (d = 3) */
+#define RSFDE_K_MV_LAST     2  /* last-axis operator pass (+ fused sine transform) */
+#define RSFDE_K_DST         3  /* sine-transform pass */
+#define RSFDE_K_DSD         4  /* transform, 1/mu scaling, transform pass */
+#define RSFDE_K_DOTS        5  /* CGS2 sweep 1 */
+#define RSFDE_K_ORTH_DOTS   6  /* CGS2 sweep 2 */
+#define RSFDE_K_ORTH_NORM   7  /* CGS2 sweep 3 + Givens */
+#define RSFDE_K_UPDATE      8  /* solution update */
+#define RSFDE_K_NCLASS      9
+
+/* Record HIP events around every launch of the kernel classes in `mask` (on the
+ * handle's stream) and reset the counters; mask 0 switches timing off.
+ * rsfde_get_timing returns, for one class, the launches timed since then, their
+ * summed milliseconds and their summed algorithmic HBM bytes (arrays read plus
+ * arrays written, each counted once). */
+int rsfde_set_timing(rsfde_handle h, unsigned mask);
+int rsfde_get_timing(rsfde_handle h, int kclass, long long* launches, double* ms, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // Host runtime of the C ABI declared in include/rsfde.h.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -19,9 +20,9 @@
 // ---------------------------------------------------------------------------
 #define RSFDE_DECL(L)                                                                        \
   template <>                                                                                \
-  hipError_t launch_pass_L<double, L>(const PassArgs&, bool, hipStream_t);                  \
+  hipError_t launch_pass_L<double, L>(const PassArgs&, bool, int, hipStream_t);             \
   template <>                                                                                \
-  hipError_t launch_pass_L<float, L>(const PassArgs&, bool, hipStream_t);                   \
+  hipError_t launch_pass_L<float, L>(const PassArgs&, bool, int, hipStream_t);              \
   template <>                                                                                \
   hipError_t launch_spectrum_L<L>(const double*, int, const cpx<double>*, double*, float*,  \
                                   double*, hipStream_t);
@@ -41,21 +42,22 @@ static bool supported_L(int L) {
 
 static hipError_t launch_pass(int L, bool fp32, const PassArgs& a, bool strided, hipStream_t s) {
   switch (L) {
-#define RSFDE_CASE(LL) \
-  case LL:             \
-    return fp32 ? launch_pass_L<float, LL>(a, strided, s) : launch_pass_L<double, LL>(a, strided, s);
+#define RSFDE_CASE(LL)                                                    \
+  case LL:                                                                \
+    return fp32 ? launch_pass_L<float, LL>(a, strided, a.var, s)          \
+                : launch_pass_L<double, LL>(a, strided, a.var, s);
     RSFDE_FOR_EACH_L(RSFDE_CASE)
 #undef RSFDE_CASE
   }
   return hipErrorInvalidValue;
 }
 
-static void pass_shape_rt(int L, bool fp32, bool strided, int* nt, int* ppt) {
+static void pass_shape_rt(int L, bool fp32, bool strided, int var, int* nt, int* ppt) {
   switch (L) {
-#define RSFDE_CASE(LL)                             \
-  case LL:                                         \
-    if (fp32) pass_shape<float, LL>(strided, nt, ppt); \
-    else pass_shape<double, LL>(strided, nt, ppt);     \
+#define RSFDE_CASE(LL)                                  \
+  case LL:                                              \
+    if (fp32) pass_shape<float, LL>(strided, var, nt, ppt); \
+    else pass_shape<double, LL>(strided, var, nt, ppt);     \
     return;
     RSFDE_FOR_EACH_L(RSFDE_CASE)
 #undef RSFDE_CASE
@@ -110,8 +112,9 @@ struct Inst {
   float* e32 = nullptr;
   void* tmp[4] = {nullptr, nullptr, nullptr, nullptr};
   GmresState* st = nullptr;
-  unsigned* counters = nullptr;  // [0] Krylov sweeps, [1] update, [2] min/max
-  double* partial = nullptr;
+  unsigned* counters = nullptr;
+  double* partial = nullptr;               // cycle-start norm and min/max partials
+  double* pk[3] = {nullptr, nullptr, nullptr};  // CGS2 sweep partials (value-major)
   double* ebar = nullptr;
   double* eminmax = nullptr;
   bool ebar_set = false;
@@ -125,25 +128,16 @@ struct Inst {
   double* fsin_e[3] = {nullptr, nullptr, nullptr};
   double* fsin_f[3] = {nullptr, nullptr, nullptr};
   int k_prev = 4;
+  int var[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // tile variant per axis and precision
 };
 
 struct TimedPass {
   hipEvent_t a, b;
   double bytes;
+  int cls;
 };
 
 }  // namespace
-
-struct rsfde_ctx {
-  int count = 0;
-  std::vector<Inst> inst;
-  hipStream_t stream = nullptr;
-  GmresSummary* pinned = nullptr;
-  bool timing = false;
-  std::vector<TimedPass> pending;
-  long long t_launches = 0;
-  double t_ms = 0, t_bytes = 0;
-};
 
 #define CK(x)                          \
   do {                                 \
@@ -159,6 +153,44 @@ struct rsfde_ctx {
     int s_ = (x);               \
     if (s_ < 0) return s_;      \
   } while (0)
+
+struct rsfde_ctx {
+  int count = 0;
+  std::vector<Inst> inst;
+  hipStream_t stream = nullptr;
+  GmresSummary* pinned = nullptr;
+  unsigned tmask = 0;
+  std::vector<TimedPass> pending;
+  std::vector<hipEvent_t> ev_free;
+  long long t_launches[RSFDE_K_NCLASS] = {0};
+  double t_ms[RSFDE_K_NCLASS] = {0}, t_bytes[RSFDE_K_NCLASS] = {0};
+};
+
+static hipError_t get_event(rsfde_ctx* h, hipEvent_t* ev) {
+  if (!h->ev_free.empty()) {
+    *ev = h->ev_free.back();
+    h->ev_free.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(ev);
+}
+
+// Launch `fn` (returning hipError_t); when class `cls` is timed, bracket it by events.
+template <typename Fn>
+static int timed_launch(rsfde_ctx* h, int cls, double bytes, Fn fn) {
+  if ((h->tmask >> cls) & 1u) {
+    hipEvent_t ea, eb;
+    CK(get_event(h, &ea));
+    CK(get_event(h, &eb));
+    CK(hipEventRecord(ea, h->stream));
+    CK(fn());
+    CK(hipEventRecord(eb, h->stream));
+    h->pending.push_back(TimedPass{ea, eb, bytes, cls});
+  } else {
+    CK(fn());
+  }
+  return RSFDE_OK;
+}
 
 // ---------------------------------------------------------------------------
 // validation and layout
@@ -219,7 +251,8 @@ static void layout(Inst& I, Bump& B) {
   I.ldv = (I.n + 63) / 64 * 64;
   I.st = B.take<GmresState>(1);
   I.counters = B.take<unsigned>(64);
-  I.partial = B.take<double>((size_t)1024 * (RSFDE_MAX_RESTART + 1));
+  I.partial = B.take<double>((size_t)4096);
+  for (int k = 0; k < 3; ++k) I.pk[k] = B.take<double>((size_t)RSFDE_PVS * (RSFDE_MAX_RESTART + 1));
   I.ebar = B.take<double>(1);
   I.eminmax = B.take<double>(2);
   for (int i = 0; i < p.d; ++i) {
@@ -269,7 +302,8 @@ static PassArgs mk_pass(const Inst& I, int axis, int op, bool fp32) {
   a.inner = inner;
   a.npencil = I.n / A.N;
   int nt, ppt;
-  pass_shape_rt(A.L, fp32, axis > 0, &nt, &ppt);
+  a.var = I.var[axis][fp32 ? 1 : 0];
+  pass_shape_rt(A.L, fp32, axis > 0, a.var, &nt, &ppt);
   if (axis == 0) {
     a.tiles_inner = 1;
     a.ntiles = (a.npencil + ppt - 1) / ppt;
@@ -314,22 +348,22 @@ static double pass_bytes(const PassArgs& a, const Inst& I, bool fp32) {
   }
 }
 
+static int op_class(int op) {
+  switch (op) {
+    case OP_MV_FIRST: return RSFDE_K_MV_FIRST;
+    case OP_MV_MID: return RSFDE_K_MV_MID;
+    case OP_MV_LAST: return RSFDE_K_MV_LAST;
+    case OP_DST: return RSFDE_K_DST;
+    default: return RSFDE_K_DSD;
+  }
+}
+
 static int run_pass(rsfde_ctx* h, const Inst& I, const PassArgs& a, bool fp32) {
   const int L = I.ax[a.axis].L;
   if (a.ntiles <= 0) return RSFDE_OK;
   if (a.ntiles > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
-  if (h->timing) {
-    hipEvent_t ea, eb;
-    CK(hipEventCreate(&ea));
-    CK(hipEventCreate(&eb));
-    CK(hipEventRecord(ea, h->stream));
-    CK(launch_pass(L, fp32, a, a.axis > 0, h->stream));
-    CK(hipEventRecord(eb, h->stream));
-    h->pending.push_back(TimedPass{ea, eb, pass_bytes(a, I, fp32)});
-  } else {
-    CK(launch_pass(L, fp32, a, a.axis > 0, h->stream));
-  }
-  return RSFDE_OK;
+  return timed_launch(h, op_class(a.op), pass_bytes(a, I, fp32),
+                      [&]() { return launch_pass(L, fp32, a, a.axis > 0, h->stream); });
 }
 
 static int flush_timing(rsfde_ctx* h) {
@@ -337,11 +371,11 @@ static int flush_timing(rsfde_ctx* h) {
     float ms = 0.f;
     CK(hipEventSynchronize(tp.b));
     CK(hipEventElapsedTime(&ms, tp.a, tp.b));
-    h->t_ms += ms;
-    h->t_bytes += tp.bytes;
-    h->t_launches += 1;
-    (void)hipEventDestroy(tp.a);
-    (void)hipEventDestroy(tp.b);
+    h->t_ms[tp.cls] += ms;
+    h->t_bytes[tp.cls] += tp.bytes;
+    h->t_launches[tp.cls] += 1;
+    h->ev_free.push_back(tp.a);
+    h->ev_free.push_back(tp.b);
   }
   h->pending.clear();
   return RSFDE_OK;
@@ -353,7 +387,8 @@ enum Chain { CH_APPLY_A = 0, CH_RHS = 1, CH_RESID = 2, CH_OPER = 3 };
 // CH_RHS: out = B E x - S x + xcoef * xin.  CH_RESID: out = (BP)^{-1}(xin - A x).
 // CH_OPER: out = (BP)^{-1} A (sc * x).  x is FP64; out is FP64.
 static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const double* x,
-                     const double* sc, const double* xin, double xcoef, double* out) {
+                     const double* sc, const double* xin, double xcoef, double* out,
+                     const GmRes* gm = nullptr, const int* stop_fl = nullptr) {
   const int d = I.d;
   const void* e = fp32 ? (const void*)I.e32 : (const void*)I.e;
   const bool prec = kind == CH_RESID || kind == CH_OPER;
@@ -370,6 +405,11 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
     a.in_x = xin;
     a.xcoef = xcoef;
     a.out_a = out;
+    if (gm) {
+      a.use_gm = 1;
+      a.gm = *gm;
+      a.sc_ptr = nullptr;
+    }
     return run_pass(h, I, a, fp32);
   }
   // first axis
@@ -381,6 +421,11 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
   a.eta = sgn * I.ax[0].eta;
   a.out_a = T[0];
   a.out_c = T[1];
+  if (gm) {
+    a.use_gm = 1;
+    a.gm = *gm;
+    a.sc_ptr = nullptr;
+  }
   CKS(run_pass(h, I, a, fp32));
   int ia = 0, ic = 1;
   if (d == 3) {
@@ -390,6 +435,7 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
     m.eta = sgn * I.ax[1].eta;
     m.out_a = T[2];
     m.out_c = T[3];
+    m.stop_fl = stop_fl;
     CKS(run_pass(h, I, m, fp32));
     ia = 2;
     ic = 3;
@@ -401,6 +447,7 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
   z.gam = kind == CH_RESID ? -1.0 : 1.0;
   z.in_x = xin;
   z.xcoef = xcoef;
+  z.stop_fl = stop_fl;
   if (!prec) {
     z.flags = FL_OUT64;
     z.out_a = out;
@@ -417,6 +464,7 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
     PassArgs t = mk_pass(I, ax, OP_DST, fp32);
     t.in_c = T[cur];
     t.out_a = T[nxt(cur)];
+    t.stop_fl = stop_fl;
     CKS(run_pass(h, I, t, fp32));
     cur = nxt(cur);
   }
@@ -424,12 +472,14 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
     PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
     t.in_c = T[cur];
     t.out_a = T[nxt(cur)];
+    t.stop_fl = stop_fl;
     CKS(run_pass(h, I, t, fp32));
     cur = nxt(cur);
   }
   for (int ax = 1; ax <= d - 1; ++ax) {
     PassArgs t = mk_pass(I, ax, OP_DST, fp32);
     t.in_c = T[cur];
+    t.stop_fl = stop_fl;
     const bool last = ax == d - 1;
     t.flags = last ? FL_OUT64 : 0;
     t.out_a = last ? (void*)out : T[nxt(cur)];
@@ -532,47 +582,71 @@ static int read_summary(rsfde_ctx* h, const Inst& I, GmresSummary* out) {
   CK(hipMemcpyAsync(h->pinned, &I.st->sum, sizeof(GmresSummary), hipMemcpyDeviceToHost, h->stream));
   CK(hipStreamSynchronize(h->stream));
   *out = *h->pinned;
-  if (h->timing) CKS(flush_timing(h));
+  if (!h->pending.empty()) CKS(flush_timing(h));
   return RSFDE_OK;
 }
 
-// Runs one GMRES cycle's iterations (speculatively chunked) after cycle_init.
+// Runs one GMRES cycle's iterations after cycle_init, launched in chunks
+// without host synchronisation inside a chunk: the chunk length is the previous
+// cycle's iteration count, then one step at a time.  Kernels of steps past
+// convergence exit on the device status (FL); the update kernel that closes a
+// chunk resolves its last step and adds V y once the cycle has finished.
 static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* S) {
   const int m = I.p.restart;
+  const int nb = kry_blocks(I.n);
   int j = 0;
+  int pending = -1;  // step the next first pass must resolve (-1: already resolved)
   int chunk = std::max(1, std::min(m, I.k_prev));
   while (true) {
     const int jend = std::min(m, j + chunk);
     for (int jj = j; jj < jend; ++jj) {
       double* vj = I.V + (int64_t)jj * I.ldv;
       double* w = I.V + (int64_t)(jj + 1) * I.ldv;
-      CKS(run_chain(h, I, CH_OPER, fp32, vj, I.st->vsc + jj, nullptr, 0.0, w));
+      GmRes g;
+      g.st = I.st;
+      g.p3 = I.pk[2];
+      g.nb3 = nb;
+      g.j = jj;
+      g.pend = jj == j ? pending : jj - 1;
+      g.m = m;
+      CKS(run_chain(h, I, CH_OPER, fp32, vj, nullptr, nullptr, 0.0, w, &g, &I.st->FL[jj]));
       KryArgs ka;
       ka.V = I.V;
       ka.ldv = I.ldv;
       ka.n = I.n;
       ka.w = w;
       ka.st = I.st;
-      ka.partial = I.partial;
-      ka.counter = I.counters;
+      ka.pa = I.pk[0];
+      ka.pb = I.pk[1];
+      ka.pc = I.pk[2];
       ka.j = jj;
       ka.m = m;
-      CK(kry_dots(ka, h->stream));
-      CK(kry_orth_dots(ka, h->stream));
-      CK(kry_orth_norm_givens(ka, h->stream));
+      const double vb = 8.0 * (double)I.n;
+      CKS(timed_launch(h, RSFDE_K_DOTS, vb * (jj + 2), [&]() { return kry_sweep(1, ka, h->stream); }));
+      CKS(timed_launch(h, RSFDE_K_ORTH_DOTS, vb * (jj + 3), [&]() { return kry_sweep(2, ka, h->stream); }));
+      CKS(timed_launch(h, RSFDE_K_ORTH_NORM, vb * (jj + 3), [&]() { return kry_sweep(3, ka, h->stream); }));
     }
-    CK(kry_update(I.V, I.ldv, I.n, x, I.st, I.counters + 1, h->stream));
+    GmRes gu;
+    gu.st = I.st;
+    gu.p3 = I.pk[2];
+    gu.nb3 = nb;
+    gu.j = jend - 1;
+    gu.pend = jend - 1;
+    gu.m = m;
+    CKS(timed_launch(h, RSFDE_K_UPDATE, 0.0, [&]() { return kry_update(I.V, I.ldv, I.n, x, gu, h->stream); }));
     CKS(read_summary(h, I, S));
     if (S->flag != GM_RUNNING) return RSFDE_OK;
     j = jend;
+    pending = -1;
     chunk = 1;
-    if (j >= m) return RSFDE_OK;  // cannot happen: the last Givens step ends the cycle
+    if (j >= m) return RSFDE_OK;  // cannot happen: the last step of a cycle is never running
   }
 }
 
 static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f_half, double* u,
                     rsfde_stats* stats) {
   if (!I.ebar_set) return RSFDE_E_STATE;
+  if ((uintptr_t)u & 15) return RSFDE_E_INVALID_ARG;
   const rsfde_params& p = I.p;
   const bool mixed = p.precision == RSFDE_MIXED;
   if (e_half != I.e) CK(hipMemcpyAsync(I.e, e_half, I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
@@ -594,8 +668,8 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
   for (int cyc = 0; cyc < max_loops; ++cyc) {
     // z = (BP)^{-1} (b - A u) in FP64 into V_0
     CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
-    CK(kry_cycle_init(I.V, I.n, I.st, I.partial, I.counters, cyc == 0 ? 1 : 0, p.rtol, inner_rtol,
-                      mixed ? 1 : 0, h->stream));
+    CK(kry_cycle_init(I.V, I.n, I.st, I.partial, cyc == 0 ? 1 : 0, p.rtol, inner_rtol,
+                      mixed ? 1 : 0, p.restart, h->stream));
     if (mixed && cyc == max_outer) {
       // final check only
       CKS(read_summary(h, I, &S));
@@ -630,6 +704,55 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
     stats->beta0 = S.beta0;
     stats->rel_pres = S.beta0 > 0 ? (mixed ? S.beta : S.res) / S.beta0 : 0.0;
   }
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// tile autotuner: time the workgroup-shape variants of a transform pass on each
+// axis (and precision) and keep the fastest.  Results do not depend on the
+// variant (pencil pairing and arithmetic are the same), only the speed does.
+// ---------------------------------------------------------------------------
+static int autotune(rsfde_ctx* h, Inst& I) {
+  const char* off = getenv("RSFDE_NO_AUTOTUNE");
+  if (off && off[0] == '1') return RSFDE_OK;
+  CK(fill_f64((double*)I.tmp[0], I.n, 0.0, h->stream));
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  const int nprec = I.p.precision == RSFDE_MIXED ? 2 : 1;
+  int status = RSFDE_OK;
+  for (int ax = 0; ax < I.d && status == RSFDE_OK; ++ax) {
+    for (int fp = 0; fp < nprec && status == RSFDE_OK; ++fp) {
+      float best = 1e30f;
+      int bestv = 0;
+      for (int v = 0; v < RSFDE_PASS_VARIANTS; ++v) {
+        I.var[ax][fp] = v;
+        PassArgs t = mk_pass(I, ax, OP_DST, fp == 1);
+        t.in_c = I.tmp[0];
+        t.out_a = I.tmp[1];
+        const int L = I.ax[ax].L;
+        hipError_t e = launch_pass(L, fp == 1, t, ax > 0, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_pass(L, fp == 1, t, ax > 0, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          g_last_hip = e;
+          status = RSFDE_E_HIP;
+          break;
+        }
+        if (ms < best * 0.97f) {
+          best = ms;
+          bestv = v;
+        }
+      }
+      I.var[ax][fp] = bestv;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return status;
 }
 
@@ -696,7 +819,7 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
     }
     I.pscale = pscale;
     if (status != RSFDE_OK) break;
-    if (kry_state_reset(I.st, I.counters, h->stream) != hipSuccess ||
+    if (kry_state_reset(I.st, h->stream) != hipSuccess ||
         hipMemsetAsync(I.counters, 0, 64 * sizeof(unsigned), h->stream) != hipSuccess) {
       g_last_hip = hipGetLastError();
       status = RSFDE_E_HIP;
@@ -719,6 +842,7 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
       status = RSFDE_E_HIP;
     }
   }
+  for (int i = 0; i < count && status == RSFDE_OK; ++i) status = autotune(h, h->inst[i]);
   if (status != RSFDE_OK) {
     (void)hipHostFree(h->pinned);
     delete h;
@@ -834,6 +958,7 @@ int rsfde_destroy(rsfde_handle h) {
     (void)hipEventDestroy(tp.a);
     (void)hipEventDestroy(tp.b);
   }
+  for (auto ev : h->ev_free) (void)hipEventDestroy(ev);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return RSFDE_OK;
@@ -996,24 +1121,45 @@ int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* 
   return RSFDE_OK;
 }
 
-int rsfde_set_timing(rsfde_handle h, int enable) {
-  if (!h) return RSFDE_E_INVALID_ARG;
-  CKS(flush_timing(h));
-  h->timing = enable != 0;
-  h->t_launches = 0;
-  h->t_ms = 0;
-  h->t_bytes = 0;
-  return RSFDE_OK;
-}
-
-int rsfde_get_timing(rsfde_handle h, long long* launches, double* ms, double* bytes) {
+int rsfde_set_timing(rsfde_handle h, unsigned mask) {
   if (!h) return RSFDE_E_INVALID_ARG;
   CK(hipStreamSynchronize(h->stream));
   CKS(flush_timing(h));
-  if (launches) *launches = h->t_launches;
-  if (ms) *ms = h->t_ms;
-  if (bytes) *bytes = h->t_bytes;
+  h->tmask = mask;
+  for (int c = 0; c < RSFDE_K_NCLASS; ++c) {
+    h->t_launches[c] = 0;
+    h->t_ms[c] = 0;
+    h->t_bytes[c] = 0;
+  }
   return RSFDE_OK;
+}
+
+int rsfde_get_timing(rsfde_handle h, int kclass, long long* launches, double* ms, double* bytes) {
+  if (!h || kclass < 0 || kclass >= RSFDE_K_NCLASS) return RSFDE_E_INVALID_ARG;
+  CK(hipStreamSynchronize(h->stream));
+  CKS(flush_timing(h));
+  if (launches) *launches = h->t_launches[kclass];
+  if (ms) *ms = h->t_ms[kclass];
+  if (bytes) *bytes = h->t_bytes[kclass];
+  return RSFDE_OK;
+}
+
+int rsfde_prescan_ebar(rsfde_handle h, int instance, int M) {
+  if (!h || instance < 0 || instance >= h->count || M < 1) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  if (!I.fe.set) return RSFDE_E_STATE;
+  CK(minmax_reset(I.eminmax, h->stream));
+  const int scans = I.fe.spec.time_dependent ? M : 1;
+  for (int m = 0; m < scans; ++m) {
+    CKS(eval_field(h, I, RSFDE_WHICH_E, (m + 0.5) * I.p.dt, I.e));
+    CK(minmax_accum(I.e, I.n, I.eminmax, I.partial, I.counters + 2, h->stream));
+  }
+  I.fe.evaluated = false;
+  double mm[2];
+  CK(hipMemcpyAsync(mm, I.eminmax, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  CK(hipStreamSynchronize(h->stream));
+  if (!(mm[0] > 0.0) || !isfinite(mm[1])) return RSFDE_E_INVALID_ARG;
+  return rsfde_set_ebar(h, instance, mm[0], mm[1]);
 }
 
 }  // extern "C"

@@ -40,15 +40,99 @@ RSFDE_PLAN(512, 8, 8, 8, 8)
 RSFDE_PLAN(768, 12, 4, 4, 4, 4, 3)
 RSFDE_PLAN(1024, 16, 16, 16, 4)
 RSFDE_PLAN(1536, 24, 8, 8, 8, 3)
-RSFDE_PLAN(2048, 16, 16, 16, 8)
+RSFDE_PLAN(2048, 8, 8, 8, 8, 4)
 RSFDE_PLAN(3072, 24, 8, 8, 8, 3, 2)
 RSFDE_PLAN(4096, 16, 16, 16, 16)
 #undef RSFDE_PLAN
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
+// Twiddles W_L^m = W_L^{m mod B} * W_L^{B floor(m/B)}: two short tables kept in
+// LDS (B + L/B entries) replace the length-L table in global memory.
+template <int L> struct TwSplit {
+  static constexpr int B = cgcd(L, 64);
+  static constexpr int NB = L / B;
+  static constexpr int size = B + NB;
+};
+
+// Fill the LDS twiddle tables from the global table tw[k] = exp(-2 pi i k / L).
+template <typename R, int L>
+__device__ __forceinline__ void twiddle_fill(cpx<R>* twl, const cpx<R>* __restrict__ tw, int tid,
+                                             int nt) {
+  using S = TwSplit<L>;
+  for (int i = tid; i < S::size; i += nt) twl[i] = i < S::B ? tw[i] : tw[(i - S::B) * S::B];
+}
+
+template <typename R, int L>
+__device__ __forceinline__ cpx<R> twiddle(const cpx<R>* twl, int m) {
+  using S = TwSplit<L>;
+  if constexpr (S::NB == 1) {
+    return twl[m];
+  } else {
+    return cmul(twl[m % S::B], twl[S::B + m / S::B]);
+  }
+}
 
 template <int L, int S> struct StageNs {
   static constexpr int value = StageNs<L, S - 1>::value * FftPlan<L>::R[S - 1];
 };
 template <int L> struct StageNs<L, 0> { static constexpr int value = 1; };
+
+template <int L, int S>
+struct TwOffset {  // first register slot of stage S
+  using P = FftPlan<L>;
+  static constexpr int value = TwOffset<L, S - 1>::value + (P::E / P::R[S - 1]) * (P::R[S - 1] - 1);
+};
+template <int L> struct TwOffset<L, 1> { static constexpr int value = 0; };
+template <int L> struct TwOffset<L, 0> { static constexpr int value = 0; };
+
+template <int L>
+struct TwTotal {
+  static constexpr int value = TwOffset<L, FftPlan<L>::NS>::value;
+};
+
+// Twiddles held in registers: each thread loads, once per kernel, exactly the
+// W_L^m its butterflies use (straight from the table, no products).
+template <typename R, int L>
+struct TwReg {
+  static constexpr int N = TwTotal<L>::value > 0 ? TwTotal<L>::value : 1;
+  cpx<R> w[N];
+  template <int S>
+  __device__ __forceinline__ void load_stage(const cpx<R>* __restrict__ g, int t) {
+    if constexpr (S < FftPlan<L>::NS) {
+      using P = FftPlan<L>;
+      constexpr int RAD = P::R[S], Ns = StageNs<L, S>::value, NB = P::E / RAD;
+      constexpr int step = L / (Ns * RAD), off = TwOffset<L, S>::value;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int k = (t + b * P::T) % Ns;
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) w[off + b * (RAD - 1) + r - 1] = g[r * k * step];
+      }
+      load_stage<S + 1>(g, t);
+    }
+  }
+  __device__ __forceinline__ void load(const cpx<R>* __restrict__ g, int t) { load_stage<1>(g, t); }
+  template <int S>
+  __device__ __forceinline__ cpx<R> get(int b, int r, int /*m*/) const {
+    constexpr int RAD = FftPlan<L>::R[S];
+    return w[TwOffset<L, S>::value + b * (RAD - 1) + r - 1];
+  }
+};
+
+// Twiddles from the two-level LDS table (plans with many twiddles per thread).
+template <typename R, int L>
+struct TwLds {
+  const cpx<R>* tab;
+  template <int S>
+  __device__ __forceinline__ cpx<R> get(int, int, int m) const { return twiddle<R, L>(tab, m); }
+};
+
+// Registers when a thread needs at most 32 twiddles, else the LDS table.
+template <int L>
+struct TwUseReg {
+  static constexpr bool value = TwTotal<L>::value <= 32;
+};
 
 // ---- small DFTs; DIR = -1 forward (e^{-2 pi i nk/R}), +1 backward ----------
 
@@ -153,11 +237,10 @@ __device__ __forceinline__ void dft(cpx<R>* v) {
   else static_assert(RAD == 2, "unsupported radix");
 }
 
-// One Stockham stage on the thread's part of one transform held in LDS.
-// tw[k] = exp(-2 pi i k / L) for k in [0, L).
-template <typename R, int L, int DIR, int S>
-__device__ __forceinline__ void fft_stage(cpx<R>* __restrict__ buf, int t,
-                                          const cpx<R>* __restrict__ tw) {
+// One Stockham stage on the thread's part of one transform held in LDS;
+// twl is the LDS twiddle table filled by twiddle_fill.
+template <typename R, int L, int DIR, int S, typename TW>
+__device__ __forceinline__ void fft_stage(cpx<R>* __restrict__ buf, int t, const TW& tw) {
   using P = FftPlan<L>;
   constexpr int RAD = P::R[S];
   constexpr int Ns = StageNs<L, S>::value;
@@ -178,7 +261,7 @@ __device__ __forceinline__ void fft_stage(cpx<R>* __restrict__ buf, int t,
       constexpr int step = L / (Ns * RAD);
 #pragma unroll
       for (int r = 1; r < RAD; ++r) {
-        cpx<R> w = tw[r * k * step];
+        cpx<R> w = tw.template get<S>(b, r, r * k * step);
         if (DIR > 0) w.y = -w.y;
         v[b * RAD + r] = cmul(v[b * RAD + r], w);
       }
@@ -197,8 +280,8 @@ __device__ __forceinline__ void fft_stage(cpx<R>* __restrict__ buf, int t,
   __syncthreads();
 }
 
-template <typename R, int L, int DIR, int S>
-__device__ __forceinline__ void fft_stages(cpx<R>* buf, int t, const cpx<R>* tw) {
+template <typename R, int L, int DIR, int S, typename TW>
+__device__ __forceinline__ void fft_stages(cpx<R>* buf, int t, const TW& tw) {
   if constexpr (S < FftPlan<L>::NS) {
     fft_stage<R, L, DIR, S>(buf, t, tw);
     fft_stages<R, L, DIR, S + 1>(buf, t, tw);
@@ -206,8 +289,9 @@ __device__ __forceinline__ void fft_stages(cpx<R>* buf, int t, const cpx<R>* tw)
 }
 
 // Full transform of the length-L sequence in `buf` (all threads of the
-// workgroup must call it together: it contains barriers).
-template <typename R, int L, int DIR>
-__device__ __forceinline__ void fft_lds(cpx<R>* buf, int t, const cpx<R>* tw) {
+// workgroup must call it together: it contains barriers).  `tw` is a TwReg or
+// TwLds twiddle provider.
+template <typename R, int L, int DIR, typename TW>
+__device__ __forceinline__ void fft_lds(cpx<R>* buf, int t, const TW& tw) {
   fft_stages<R, L, DIR, 0>(buf, t, tw);
 }

@@ -88,11 +88,18 @@ k_fields_eval(const FieldDev E, const FieldDev F, int which, const GridDev g, do
   int jc[3] = {0, 0, 0};
   int Ncl[3] = {1, 1, 1};
   double x[3] = {0.0, 0.0, 0.0};
-  int64_t r = idx;
+  uint64_t r = (uint64_t)idx;
   for (int i = 0; i < d; ++i) {
-    const int ni = g.closure ? g.N[i] + 2 : g.N[i];
-    const int64_t ji = r % ni;
-    r /= ni;
+    const unsigned ni = (unsigned)(g.closure ? g.N[i] + 2 : g.N[i]);
+    unsigned ji;
+    if (r < 0xffffffffull) {
+      const unsigned r32 = (unsigned)r;
+      ji = r32 % ni;
+      r = r32 / ni;
+    } else {
+      ji = (unsigned)(r % ni);
+      r /= ni;
+    }
     jc[i] = (int)ji + (g.closure ? 0 : 1);
     Ncl[i] = g.N[i] + 2;
     x[i] = g.lo[i] + (double)jc[i] * g.h[i];
@@ -162,10 +169,18 @@ k_compute_F(const double* __restrict__ fcl, const GridDev g, double a0, double a
   const double al[3] = {a0, a1, a2};
   int j[3] = {0, 0, 0};
   int64_t sc[3] = {0, 0, 0};
-  int64_t r = idx, stride = 1;
+  uint64_t r = (uint64_t)idx;
+  int64_t stride = 1;
   for (int i = 0; i < d; ++i) {
-    j[i] = (int)(r % g.N[i]) + 1;
-    r /= g.N[i];
+    const unsigned ni = (unsigned)g.N[i];
+    if (r < 0xffffffffull) {
+      const unsigned r32 = (unsigned)r;
+      j[i] = (int)(r32 % ni) + 1;
+      r = r32 / ni;
+    } else {
+      j[i] = (int)(r % ni) + 1;
+      r /= ni;
+    }
     sc[i] = stride;
     stride *= (g.N[i] + 2);
   }
@@ -207,8 +222,9 @@ hipError_t minmax_reset(double* mm, hipStream_t s) {
   return hipGetLastError();
 }
 
+// per-block extremes (no cross-block synchronisation)
 __global__ void __launch_bounds__(256)
-k_minmax(const double* __restrict__ e, int64_t n, double* mm, double* partial, unsigned* counter) {
+k_minmax_part(const double* __restrict__ e, int64_t n, double* __restrict__ partial) {
   double lo = INFINITY, hi = -INFINITY;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -222,7 +238,6 @@ k_minmax(const double* __restrict__ e, int64_t n, double* mm, double* partial, u
     hi = fmax(hi, __shfl_xor(hi, off, 64));
   }
   __shared__ double sl[4], sh[4];
-  __shared__ int amlast;
   if ((threadIdx.x & 63) == 0) {
     sl[threadIdx.x >> 6] = lo;
     sh[threadIdx.x >> 6] = hi;
@@ -236,30 +251,46 @@ k_minmax(const double* __restrict__ e, int64_t n, double* mm, double* partial, u
     partial[2 * blockIdx.x] = lo;
     partial[2 * blockIdx.x + 1] = hi;
   }
-  __threadfence();
+}
+
+// one workgroup folds the block extremes into the running mm[0..1]
+__global__ void __launch_bounds__(256)
+k_minmax_fin(const double* __restrict__ partial, int nblocks, double* mm) {
+  double lo = INFINITY, hi = -INFINITY;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    lo = fmin(lo, partial[2 * b]);
+    hi = fmax(hi, partial[2 * b + 1]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  __shared__ double sl[4], sh[4];
+  if ((threadIdx.x & 63) == 0) {
+    sl[threadIdx.x >> 6] = lo;
+    sh[threadIdx.x >> 6] = hi;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) amlast = atomicAdd(counter, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!amlast) return;
-  __threadfence();
   if (threadIdx.x == 0) {
     double L = mm[0], H = mm[1];
-    for (unsigned b = 0; b < gridDim.x; ++b) {
-      L = fmin(L, partial[2 * b]);
-      H = fmax(H, partial[2 * b + 1]);
+    for (int w = 0; w < 4; ++w) {
+      L = fmin(L, sl[w]);
+      H = fmax(H, sh[w]);
     }
     mm[0] = L;
     mm[1] = H;
-    *counter = 0u;
   }
 }
 
 hipError_t minmax_accum(const double* e, int64_t n, double* mm, double* partial, unsigned* counter,
                         hipStream_t s) {
+  (void)counter;
   int64_t b = (n + 2047) / 2048;
   if (b > 512) b = 512;
   if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_minmax, dim3((unsigned)b), dim3(256), 0, s, e, n, mm, partial, counter);
+  hipLaunchKernelGGL(k_minmax_part, dim3((unsigned)b), dim3(256), 0, s, e, n, partial);
+  hipLaunchKernelGGL(k_minmax_fin, dim3(1), dim3(256), 0, s, partial, (int)b, mm);
   return hipGetLastError();
 }
 

@@ -1,26 +1,28 @@
-// Arnoldi (CGS2), Givens least-squares and solution-update kernels.
+// Arnoldi (CGS2) sweeps, cycle start and solution update.
+//
+// Each sweep writes one partial sum per block and value (value-major, no
+// cross-block synchronisation).  The next sweep adds those partials in a fixed
+// order in its prologue (every block redundantly; the sum is deterministic),
+// so no single-block finish kernel sits between sweeps.
 #include <math.h>
 
 #include "krylov.h"
 
-#define PST (RSFDE_MAX_RESTART + 1)  // partial-sum stride per block
-#define NWAVE (RSFDE_KRY_THREADS / 64)
+// threads per block for a sweep handling up to KM basis vectors
+template <int KM> struct SweepNT { static constexpr int value = KM <= 8 ? 1024 : (KM <= 16 ? 512 : 256); };
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
-
-// Block-level sums of acc[0..nv) written to dst[0..nv) (fixed order).
-template <int KM>
-__device__ __forceinline__ void block_partials(const double (&acc)[KM], int nv, double* dst) {
-  __shared__ double sh[NWAVE][KM];
+// Block sums of acc[0..nv) (fixed order); result in res[0..nv) (shared).
+template <int KM, int NT>
+__device__ __forceinline__ void block_sums(const double (&acc)[KM], int nv, double* res) {
+  constexpr int NW = NT / 64;
+  __shared__ double sh[NW][KM];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
     if (k < nv) {
-      const double x = wave_sum(acc[k]);
+      double x = acc[k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
       if (lane == 0) sh[wv][k] = x;
     }
   }
@@ -28,283 +30,293 @@ __device__ __forceinline__ void block_partials(const double (&acc)[KM], int nv, 
   if ((int)threadIdx.x < nv) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < NWAVE; ++w) s += sh[w][threadIdx.x];
-    dst[threadIdx.x] = s;
+    for (int w = 0; w < NW; ++w) s += sh[w][threadIdx.x];
+    res[threadIdx.x] = s;
   }
-}
-
-// True in the one block that finishes last; every block must call it.
-__device__ __forceinline__ bool last_block(unsigned* counter) {
-  __shared__ int amlast;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned tk = atomicAdd(counter, 1u);
-    amlast = (tk == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (amlast) __threadfence();
-  return amlast != 0;
-}
-
-// In the last block: out[k] = sum over blocks of partial[b*PST + k], k < nv, in a
-// fixed order; result left in `res` (shared, length >= nv).  Resets the counter.
-__device__ __forceinline__ void final_sums(const double* partial, int nblocks, int nv, double* res,
-                                          unsigned* counter) {
-  __shared__ double sh[RSFDE_KRY_THREADS];
-  int KS = 1;
-  while (KS < nv) KS <<= 1;
-  const int ng = RSFDE_KRY_THREADS / KS;
-  const int k = threadIdx.x % KS, g = threadIdx.x / KS;
-  double s = 0.0;
-  if (k < nv && g < ng) {
-    for (int b = g; b < nblocks; b += ng) s += partial[(int64_t)b * PST + k];
-  }
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  if ((int)threadIdx.x < nv) {
-    double t = 0.0;
-    for (int gg = 0; gg < ng; ++gg) t += sh[gg * KS + threadIdx.x];
-    res[threadIdx.x] = t;
-  }
-  if (threadIdx.x == 0) *counter = 0u;
   __syncthreads();
 }
 
-// ---- cycle start: beta = ||v0||, g = beta e_1, v0 scale 1/beta ---------------
-__global__ void __launch_bounds__(RSFDE_KRY_THREADS)
-k_cycle_init(const double* __restrict__ v0, int64_t n, GmresState* st, double* partial,
-             unsigned* counter, int first, double rtol, double inner_rtol, int mixed) {
+// res[k] = sum over the nb blocks' partials of value k (requires nb <= NT).
+template <int KM, int NT>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, int nv,
+                                                double* res) {
+  double acc[KM];
+#pragma unroll
+  for (int k = 0; k < KM; ++k)
+    acc[k] = ((int)threadIdx.x < nb && k < nv) ? part[k * RSFDE_PVS + threadIdx.x] : 0.0;
+  block_sums<KM, NT>(acc, nv, res);
+}
+
+// ---- ||v||^2 partials and cycle start -------------------------------------------------
+__global__ void __launch_bounds__(1024)
+k_norm_part(const double* __restrict__ v0, int64_t n, double* __restrict__ partial) {
   double acc[1] = {0.0};
-  const int64_t stride = (int64_t)gridDim.x * RSFDE_KRY_THREADS;
-  for (int64_t i = (int64_t)blockIdx.x * RSFDE_KRY_THREADS + threadIdx.x; i < n; i += stride) {
-    const double x = v0[i];
-    acc[0] += x * x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const double2* __restrict__ v2 = (const double2*)v0;
+  const int64_t n2 = n >> 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+    const double2 x = v2[i];
+    acc[0] += x.x * x.x + x.y * x.y;
   }
-  block_partials<1>(acc, 1, partial + (int64_t)blockIdx.x * PST);
-  if (!last_block(counter)) return;
-  __shared__ double res[RSFDE_MAX_RESTART + 1];
-  final_sums(partial, gridDim.x, 1, res, counter);
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) acc[0] += v0[n - 1] * v0[n - 1];
+  __shared__ double res[1];
+  block_sums<1, 1024>(acc, 1, res);
+  if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
+}
+
+// beta = ||v0||, gamma_0 = beta, vsc[0] = 1/beta, FL[0] = status, FL[1..m] unset
+__global__ void __launch_bounds__(256)
+k_cycle_init_fin(const double* __restrict__ partial, int nblocks, GmresState* st, int first,
+                 double rtol, double inner_rtol, int mixed, int m) {
+  __shared__ double res[1];
+  reduce_partials<1, 256>(partial, nblocks, 1, res);
+  if ((int)threadIdx.x >= 1 && (int)threadIdx.x <= m) st->FL[threadIdx.x] = GM_UNSET;
   if (threadIdx.x == 0) {
     const double beta = sqrt(res[0]);
     GmresSummary& S = st->sum;
-    if (first) S.beta0 = beta;
+    const double beta0 = first ? beta : S.beta0;
+    S.beta0 = beta0;
     S.beta = beta;
     S.res = beta;
     S.k = 0;
-    S.applied = 0;
-    S.thr = mixed ? inner_rtol * beta : rtol * S.beta0;
-    st->g[0] = beta;
+    S.thr = mixed ? inner_rtol * beta : rtol * beta0;
+    st->kfin = 0;
+    st->gam[0] = beta;
     st->vsc[0] = beta > 0.0 ? 1.0 / beta : 0.0;
-    if (!isfinite(beta)) S.flag = GM_NONFINITE;
-    else if (beta == 0.0 || (!first && beta <= rtol * S.beta0)) S.flag = GM_CONVERGED;
-    else S.flag = GM_RUNNING;
+    int flag;
+    if (!isfinite(beta)) flag = GM_NONFINITE;
+    else if (beta == 0.0 || (!first && beta <= rtol * beta0)) flag = GM_CONVERGED;
+    else flag = GM_RUNNING;
+    S.flag = flag;
+    st->FL[0] = flag;
   }
 }
 
-// ---- CGS2 sweep 1: h = V^T w --------------------------------------------------
+// ---- CGS2 sweep 1: partials of Vbar^T w ---------------------------------------------------
 template <int KM>
-__global__ void __launch_bounds__(RSFDE_KRY_THREADS) k_dots(const KryArgs a) {
-  GmresState* st = a.st;
-  if (st->sum.flag != GM_RUNNING) return;
+__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep1(const KryArgs a) {
+  constexpr int NT = SweepNT<KM>::value;
+  if (a.st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
   double acc[KM];
 #pragma unroll
   for (int k = 0; k < KM; ++k) acc[k] = 0.0;
   const double* __restrict__ w = a.w;
   const double* __restrict__ V = a.V;
-  const int64_t stride = (int64_t)gridDim.x * RSFDE_KRY_THREADS;
-  for (int64_t i = (int64_t)blockIdx.x * RSFDE_KRY_THREADS + threadIdx.x; i < a.n; i += stride) {
-    const double wi = w[i];
+  const int64_t stride = (int64_t)gridDim.x * NT;
+  const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
+  const double2* __restrict__ w2 = (const double2*)w;
+  const double2* __restrict__ V2 = (const double2*)V;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n2; i += stride) {
+    const double2 wi = w2[i];
 #pragma unroll
     for (int k = 0; k < KM; ++k)
-      if (k < nv) acc[k] += V[k * a.ldv + i] * wi;
+      if (k < nv) {
+        const double2 v = V2[k * ld2 + i];
+        acc[k] += v.x * wi.x + v.y * wi.y;
+      }
   }
-  block_partials<KM>(acc, nv, a.partial + (int64_t)blockIdx.x * PST);
-  if (!last_block(a.counter)) return;
-  __shared__ double res[RSFDE_MAX_RESTART + 1];
-  final_sums(a.partial, gridDim.x, nv, res, a.counter);
-  if ((int)threadIdx.x < nv) st->h[threadIdx.x] = res[threadIdx.x] * st->vsc[threadIdx.x];
+  if ((a.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t i = a.n - 1;
+    for (int k = 0; k < KM; ++k)
+      if (k < nv) acc[k] += V[k * a.ldv + i] * w[i];
+  }
+  __shared__ double res[KM];
+  block_sums<KM, NT>(acc, nv, res);
+  if ((int)threadIdx.x < nv) a.pa[threadIdx.x * RSFDE_PVS + blockIdx.x] = res[threadIdx.x];
 }
 
-// ---- CGS2 sweep 2: w -= V h ; h2 = V^T w ----------------------------------------
+// ---- CGS2 sweep 2: h = Vbar^T w / |v| ; w -= V h ; partials of Vbar^T w ------------------
 template <int KM>
-__global__ void __launch_bounds__(RSFDE_KRY_THREADS) k_orth_dots(const KryArgs a) {
+__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep2(const KryArgs a) {
+  constexpr int NT = SweepNT<KM>::value;
   GmresState* st = a.st;
-  if (st->sum.flag != GM_RUNNING) return;
+  if (st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
   __shared__ double cf[KM];
-  if ((int)threadIdx.x < KM) cf[threadIdx.x] = (int)threadIdx.x < nv ? st->h[threadIdx.x] * st->vsc[threadIdx.x] : 0.0;
+  reduce_partials<KM, NT>(a.pa, gridDim.x, nv, cf);
+  if ((int)threadIdx.x < nv) {
+    const double sc = st->vsc[threadIdx.x];
+    const double h = cf[threadIdx.x] * sc;
+    if (blockIdx.x == 0) st->h[threadIdx.x] = h;
+    cf[threadIdx.x] = h * sc;
+  }
   __syncthreads();
   double acc[KM];
 #pragma unroll
   for (int k = 0; k < KM; ++k) acc[k] = 0.0;
   double* __restrict__ w = a.w;
   const double* __restrict__ V = a.V;
-  const int64_t stride = (int64_t)gridDim.x * RSFDE_KRY_THREADS;
-  for (int64_t i = (int64_t)blockIdx.x * RSFDE_KRY_THREADS + threadIdx.x; i < a.n; i += stride) {
-    double wi = w[i];
+  const int64_t stride = (int64_t)gridDim.x * NT;
+  const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
+  double2* __restrict__ w2 = (double2*)w;
+  const double2* __restrict__ V2 = (const double2*)V;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n2; i += stride) {
+    double2 wi = w2[i];
+    constexpr int KR = KM <= 16 ? KM : 1;  // basis values kept in registers
+    double2 vk[KR];
 #pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (k < nv) {
+        const double2 v = V2[k * ld2 + i];
+        if constexpr (KM <= 16) vk[k] = v;
+        wi.x -= cf[k] * v.x;
+        wi.y -= cf[k] * v.y;
+      }
+    w2[i] = wi;
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (k < nv) {
+        double2 v;
+        if constexpr (KM <= 16) v = vk[k];
+        else v = V2[k * ld2 + i];
+        acc[k] += v.x * wi.x + v.y * wi.y;
+      }
+  }
+  if ((a.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t i = a.n - 1;
+    double wi = w[i];
     for (int k = 0; k < KM; ++k)
       if (k < nv) wi -= cf[k] * V[k * a.ldv + i];
     w[i] = wi;
-#pragma unroll
     for (int k = 0; k < KM; ++k)
       if (k < nv) acc[k] += V[k * a.ldv + i] * wi;
   }
-  block_partials<KM>(acc, nv, a.partial + (int64_t)blockIdx.x * PST);
-  if (!last_block(a.counter)) return;
-  __shared__ double res[RSFDE_MAX_RESTART + 1];
-  final_sums(a.partial, gridDim.x, nv, res, a.counter);
-  if ((int)threadIdx.x < nv) st->h2[threadIdx.x] = res[threadIdx.x] * st->vsc[threadIdx.x];
+  __shared__ double res[KM];
+  block_sums<KM, NT>(acc, nv, res);
+  if ((int)threadIdx.x < nv) a.pb[threadIdx.x * RSFDE_PVS + blockIdx.x] = res[threadIdx.x];
 }
 
-// ---- CGS2 sweep 3: w -= V h2 ; ||w|| ; Givens update of the least-squares problem
+// ---- CGS2 sweep 3: h2 = Vbar^T w / |v| ; w -= V h2 ; partials of ||w||^2 -----------------
 template <int KM>
-__global__ void __launch_bounds__(RSFDE_KRY_THREADS) k_orth_norm_givens(const KryArgs a) {
+__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep3(const KryArgs a) {
+  constexpr int NT = SweepNT<KM>::value;
   GmresState* st = a.st;
-  if (st->sum.flag != GM_RUNNING) return;
+  if (st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
   __shared__ double cf[KM];
-  if ((int)threadIdx.x < KM) cf[threadIdx.x] = (int)threadIdx.x < nv ? st->h2[threadIdx.x] * st->vsc[threadIdx.x] : 0.0;
+  reduce_partials<KM, NT>(a.pb, gridDim.x, nv, cf);
+  if ((int)threadIdx.x < nv) {
+    const double sc = st->vsc[threadIdx.x];
+    const double h2 = cf[threadIdx.x] * sc;
+    if (blockIdx.x == 0) st->h2[threadIdx.x] = h2;
+    cf[threadIdx.x] = h2 * sc;
+  }
   __syncthreads();
   double acc[1] = {0.0};
   double* __restrict__ w = a.w;
   const double* __restrict__ V = a.V;
-  const int64_t stride = (int64_t)gridDim.x * RSFDE_KRY_THREADS;
-  for (int64_t i = (int64_t)blockIdx.x * RSFDE_KRY_THREADS + threadIdx.x; i < a.n; i += stride) {
-    double wi = w[i];
+  const int64_t stride = (int64_t)gridDim.x * NT;
+  const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
+  double2* __restrict__ w2 = (double2*)w;
+  const double2* __restrict__ V2 = (const double2*)V;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n2; i += stride) {
+    double2 wi = w2[i];
 #pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (k < nv) {
+        const double2 v = V2[k * ld2 + i];
+        wi.x -= cf[k] * v.x;
+        wi.y -= cf[k] * v.y;
+      }
+    w2[i] = wi;
+    acc[0] += wi.x * wi.x + wi.y * wi.y;
+  }
+  if ((a.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t i = a.n - 1;
+    double wi = w[i];
     for (int k = 0; k < KM; ++k)
       if (k < nv) wi -= cf[k] * V[k * a.ldv + i];
     w[i] = wi;
     acc[0] += wi * wi;
   }
-  block_partials<1>(acc, 1, a.partial + (int64_t)blockIdx.x * PST);
-  if (!last_block(a.counter)) return;
-  __shared__ double res[RSFDE_MAX_RESTART + 1];
-  final_sums(a.partial, gridDim.x, 1, res, a.counter);
-  if (threadIdx.x != 0) return;
-  const int j = a.j;
-  const int MX = RSFDE_MAX_RESTART;
-  double hc[RSFDE_MAX_RESTART + 1];
-  for (int i = 0; i <= j; ++i) hc[i] = st->h[i] + st->h2[i];
-  const double hn = sqrt(res[0]);
-  double hsz = 0.0;
-  for (int i = 0; i <= j; ++i) hsz = fmax(hsz, fabs(hc[i]));
-  const bool breakdown = !(hn > 1e-14 * hsz);
-  // previous rotations
-  for (int i = 0; i < j; ++i) {
-    const double p = hc[i], q = hc[i + 1];
-    hc[i] = st->cs[i] * p + st->sn[i] * q;
-    hc[i + 1] = -st->sn[i] * p + st->cs[i] * q;
-  }
-  const double r = hypot(hc[j], hn);
-  const double c = r > 0.0 ? hc[j] / r : 1.0;
-  const double sgiv = r > 0.0 ? hn / r : 0.0;
-  st->cs[j] = c;
-  st->sn[j] = sgiv;
-  for (int i = 0; i < j; ++i) st->Rm[j * MX + i] = hc[i];
-  st->Rm[j * MX + j] = r;
-  const double gj = st->g[j];
-  st->g[j] = c * gj;
-  st->g[j + 1] = -sgiv * gj;
-  st->vsc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-  GmresSummary& S = st->sum;
-  const double rr = fabs(st->g[j + 1]);
-  S.res = rr;
-  int flag;
-  if (!isfinite(rr) || !isfinite(r)) flag = GM_NONFINITE;
-  else if (rr <= S.thr) flag = GM_CONVERGED;
-  else if (breakdown) flag = GM_BREAKDOWN;
-  else if (j + 1 >= a.m) flag = GM_CYCLE_FULL;
-  else flag = GM_RUNNING;
-  if (flag != GM_RUNNING && flag != GM_NONFINITE) {
-    const int k = j + 1;
-    // back substitution R y = g
-    for (int i = k - 1; i >= 0; --i) {
-      double s = st->g[i];
-      for (int l = i + 1; l < k; ++l) s -= st->Rm[l * MX + i] * st->y[l];
-      st->y[i] = s / st->Rm[i * MX + i];
-    }
-    S.k = k;
-  }
-  S.flag = flag;
+  __shared__ double res[1];
+  block_sums<1, NT>(acc, 1, res);
+  if (threadIdx.x == 0) a.pc[blockIdx.x] = res[0];
 }
 
-// ---- x += V y (once per cycle) ---------------------------------------------------
-__global__ void __launch_bounds__(RSFDE_KRY_THREADS)
+// ---- resolve the last launched step; x += V y when the cycle has finished ----------------
+__global__ void __launch_bounds__(256)
 k_update(const double* __restrict__ V, int64_t ldv, int64_t n, double* __restrict__ x,
-         GmresState* st, unsigned* counter) {
-  const GmresSummary S = st->sum;
-  if (S.flag == GM_RUNNING || S.flag == GM_NONFINITE || S.applied) return;
-  const int k = S.k;
+         const GmRes g) {
+  __shared__ GmOut o;
+  __shared__ double ysh[RSFDE_MAX_RESTART];
   __shared__ double cf[RSFDE_MAX_RESTART];
-  if ((int)threadIdx.x < k) cf[threadIdx.x] = st->y[threadIdx.x] * st->vsc[threadIdx.x];
+  gm_prologue(g, &o, ysh, true);
+  const int flag = o.flag, k = o.k;
+  if (flag == GM_RUNNING || flag == GM_NONFINITE || k <= 0) return;
+  if ((int)threadIdx.x < k) cf[threadIdx.x] = ysh[threadIdx.x] * g.st->vsc[threadIdx.x];
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * RSFDE_KRY_THREADS;
-  for (int64_t i = (int64_t)blockIdx.x * RSFDE_KRY_THREADS + threadIdx.x; i < n; i += stride) {
-    double xi = x[i];
-    for (int l = 0; l < k; ++l) xi += cf[l] * V[l * ldv + i];
-    x[i] = xi;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t n2 = n >> 1, ld2 = ldv >> 1;
+  double2* __restrict__ x2 = (double2*)x;
+  const double2* __restrict__ V2 = (const double2*)V;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+    double2 xi = x2[i];
+    for (int l = 0; l < k; ++l) {
+      const double2 v = V2[l * ld2 + i];
+      xi.x += cf[l] * v.x;
+      xi.y += cf[l] * v.y;
+    }
+    x2[i] = xi;
   }
-  if (!last_block(counter)) return;
-  if (threadIdx.x == 0) {
-    st->sum.applied = 1;
-    *counter = 0u;
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double xi = x[n - 1];
+    for (int l = 0; l < k; ++l) xi += cf[l] * V[l * ldv + n - 1];
+    x[n - 1] = xi;
   }
 }
 
-__global__ void k_state_reset(GmresState* st, unsigned* counter) {
+__global__ void k_state_reset(GmresState* st) {
   if (threadIdx.x == 0) {
     st->sum.flag = GM_RUNNING;
     st->sum.k = 0;
-    st->sum.applied = 1;
     st->sum.beta0 = 0.0;
     st->sum.beta = 0.0;
     st->sum.thr = 0.0;
     st->sum.res = 0.0;
-    *counter = 0u;
+    st->kfin = 0;
   }
+  if (threadIdx.x <= RSFDE_MAX_RESTART) st->FL[threadIdx.x] = GM_UNSET;
 }
 
-// ---- launchers --------------------------------------------------------------------
-hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial, unsigned* counter,
-                          int first, double rtol, double inner_rtol, int mixed, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_init, dim3(kry_blocks(n)), dim3(RSFDE_KRY_THREADS), 0, s, v0, n, st,
-                     partial, counter, first, rtol, inner_rtol, mixed);
+// ---- launchers ---------------------------------------------------------------------------
+hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial, int first,
+                          double rtol, double inner_rtol, int mixed, int m, hipStream_t s) {
+  const int nb = kry_blocks(n);
+  hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(1024), 0, s, v0, n, partial);
+  hipLaunchKernelGGL(k_cycle_init_fin, dim3(1), dim3(256), 0, s, partial, nb, st, first, rtol,
+                     inner_rtol, mixed, m);
   return hipGetLastError();
 }
 
-#define KRY_DISPATCH(KERNEL, a, s)                                                              \
-  do {                                                                                          \
-    const int nv = (a).j + 1;                                                                   \
-    const dim3 g(kry_blocks((a).n)), b(RSFDE_KRY_THREADS);                                       \
-    if (nv <= 8) hipLaunchKernelGGL(KERNEL<8>, g, b, 0, s, a);                                  \
-    else if (nv <= 16) hipLaunchKernelGGL(KERNEL<16>, g, b, 0, s, a);                           \
-    else if (nv <= 32) hipLaunchKernelGGL(KERNEL<32>, g, b, 0, s, a);                           \
-    else hipLaunchKernelGGL(KERNEL<64>, g, b, 0, s, a);                                         \
+#define KRY_SWEEP(KERNEL, nv, g, a, s)                                                         \
+  do {                                                                                         \
+    if ((nv) <= 8) hipLaunchKernelGGL(KERNEL<8>, g, dim3(SweepNT<8>::value), 0, s, a);         \
+    else if ((nv) <= 16) hipLaunchKernelGGL(KERNEL<16>, g, dim3(SweepNT<16>::value), 0, s, a); \
+    else if ((nv) <= 32) hipLaunchKernelGGL(KERNEL<32>, g, dim3(SweepNT<32>::value), 0, s, a); \
+    else hipLaunchKernelGGL(KERNEL<64>, g, dim3(SweepNT<64>::value), 0, s, a);                 \
   } while (0)
 
-hipError_t kry_dots(const KryArgs& a, hipStream_t s) {
-  KRY_DISPATCH(k_dots, a, s);
+hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s) {
+  const int nv = a.j + 1;
+  const dim3 g(kry_blocks(a.n));
+  if (which == 1) KRY_SWEEP(k_sweep1, nv, g, a, s);
+  else if (which == 2) KRY_SWEEP(k_sweep2, nv, g, a, s);
+  else KRY_SWEEP(k_sweep3, nv, g, a, s);
   return hipGetLastError();
 }
-hipError_t kry_orth_dots(const KryArgs& a, hipStream_t s) {
-  KRY_DISPATCH(k_orth_dots, a, s);
+
+hipError_t kry_update(const double* V, int64_t ldv, int64_t n, double* x, const GmRes& g,
+                      hipStream_t s) {
+  int64_t nb = (n / 2 + 1023) / 1024;
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_update, dim3((unsigned)nb), dim3(256), 0, s, V, ldv, n, x, g);
   return hipGetLastError();
 }
-hipError_t kry_orth_norm_givens(const KryArgs& a, hipStream_t s) {
-  KRY_DISPATCH(k_orth_norm_givens, a, s);
-  return hipGetLastError();
-}
-hipError_t kry_update(const double* V, int64_t ldv, int64_t n, double* x, GmresState* st,
-                      unsigned* counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(kry_blocks(n)), dim3(RSFDE_KRY_THREADS), 0, s, V, ldv, n, x, st,
-                     counter);
-  return hipGetLastError();
-}
-hipError_t kry_state_reset(GmresState* st, unsigned* counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st, counter);
+
+hipError_t kry_state_reset(GmresState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(128), 0, s, st);
   return hipGetLastError();
 }

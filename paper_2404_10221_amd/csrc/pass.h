@@ -12,8 +12,11 @@
 // matvec A v = B_alpha E v + S_alpha v and the preconditioner solve are chains of
 // such passes (one sweep per axis and per transform direction).
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 #include "fft.h"
+#include "krylov.h"
 
 enum : int { OP_MV_FIRST = 0, OP_MV_MID = 1, OP_MV_LAST = 2, OP_DST = 3, OP_DSD = 4 };
 enum : int {
@@ -49,6 +52,10 @@ struct PassArgs {
   const void* wq[3];     // eta_i q_i / lambda_i per axis (precision R)
   const double* ebar;    // device scalar ebar
   double pscale;         // prod_i 1/L_i: normalisation of the two sine transforms
+  int var;               // host only: workgroup-shape variant
+  int use_gm;            // first operator pass of an Arnoldi step: resolve the previous step
+  GmRes gm;              // (input scale = vsc[j] from that resolve; exit when the cycle ended)
+  const int* stop_fl;    // other passes of the step: exit unless *stop_fl == running
 };
 
 template <typename R>
@@ -79,15 +86,19 @@ __device__ __forceinline__ void set_comp(cpx<R>& z, int c, R v) {
 }
 
 // Pencils packed per workgroup: F complex transforms, i.e. 2F real pencils.
-template <typename R, int L, bool STRIDED>
+// Variant VAR halves F VAR times; the host picks a variant per axis by timing
+// them at setup (the tile autotuner).
+#define RSFDE_PASS_VARIANTS 3
+template <typename R, int L, bool STRIDED, int VAR>
 struct PassShape {
   static constexpr int T = FftPlan<L>::T;
   static constexpr int bytes_per_fft = (L + 1) * (int)sizeof(cpx<R>);
-  static constexpr int cap = STRIDED ? 160 * 1024 : 80 * 1024;
-  static constexpr int want = STRIDED ? (512 / T > 4 ? 512 / T : 4) : (256 / T > 1 ? 256 / T : 1);
+  static constexpr int cap = 160 * 1024 - TwSplit<L>::size * (int)sizeof(cpx<R>) - L * (int)sizeof(R);
+  static constexpr int want = 512 / T > 1 ? 512 / T : 1;
   static constexpr int lim = cap / bytes_per_fft;
-  static constexpr int F0 = want < lim ? want : lim;
-  static constexpr int F1 = F0 * T > 1024 ? 1024 / T : F0;
+  static constexpr int F0a = want < lim ? want : lim;
+  static constexpr int F0 = F0a * T > 1024 ? 1024 / T : F0a;
+  static constexpr int F1 = F0 >> VAR;
   static constexpr int F = F1 < 1 ? 1 : F1;
   static constexpr int NT = F * T;
 };
@@ -99,9 +110,18 @@ rsfde_pass_kernel(const PassArgs a) {
   constexpr int T = P::T, E = P::E, NT = F * T, LP = L + 1, PT = 2 * F;
   constexpr int NE = STRIDED ? E : E / 2;  // element slots per thread
   __shared__ cpx<R> lds[F * LP];
+  __shared__ cpx<R> twl[TwUseReg<L>::value ? 1 : TwSplit<L>::size];
+  __shared__ R chs[L];  // circulant spectrum / L (operator passes)
 
-  const cpx<R>* __restrict__ tw = (const cpx<R>*)a.tw;
   const int tid = threadIdx.x;
+  using TWP = typename std::conditional<TwUseReg<L>::value, TwReg<R, L>, TwLds<R, L>>::type;
+  TWP tw;
+  if constexpr (TwUseReg<L>::value) {
+    tw.load((const cpx<R>*)a.tw, tid % FftPlan<L>::T);
+  } else {
+    twiddle_fill<R, L>(twl, (const cpx<R>*)a.tw, tid, NT);
+    tw.tab = twl;
+  }
   const int f = tid / T;
   const int t = tid - f * T;
   cpx<R>* buf = lds + f * LP;
@@ -135,9 +155,22 @@ rsfde_pass_kernel(const PassArgs a) {
   auto c_row = [&](int comp) -> int64_t { return row0 + 2 * f + comp; };
 
   R sc = (R)1;
-  if (a.sc_ptr) sc = (R)(*a.sc_ptr);
+  if (a.use_gm) {
+    __shared__ GmOut go;
+    __shared__ double gy[RSFDE_MAX_RESTART];
+    gm_prologue(a.gm, &go, gy, false);
+    if (go.flag != GM_RUNNING) return;  // same value in every thread
+    sc = (R)go.sc;
+  } else {
+    if (a.stop_fl && *a.stop_fl != GM_RUNNING) return;
+    if (a.sc_ptr) sc = (R)(*a.sc_ptr);
+  }
   const R bd = (R)a.bd, bo = (R)a.bo, eta = (R)a.eta;
-  const R* __restrict__ chat = (const R*)a.chat;
+  const R* __restrict__ chat = chs;
+  if (a.op <= OP_MV_LAST) {
+    const R* __restrict__ cg = (const R*)a.chat;
+    for (int k = tid; k < L; k += NT) chs[k] = cg[k];
+  }
 
   cpx<R> ra[STRIDED ? 1 : NE];  // contiguous: packed pair per slot
   R rs[STRIDED ? NE : 1];       // strided: one value per slot
@@ -439,31 +472,49 @@ rsfde_pass_kernel(const PassArgs a) {
 // Host launcher for one (precision, length); defined in the per-length
 // instantiation units.  Returns a hipError_t.
 template <typename R, int L>
-hipError_t launch_pass_L(const PassArgs& a, bool strided, hipStream_t s);
+hipError_t launch_pass_L(const PassArgs& a, bool strided, int var, hipStream_t s);
 
-// Workgroup shape the launcher uses (threads, pencils per tile).
+// Workgroup shape of a variant (threads, pencils per tile).
 template <typename R, int L>
-inline void pass_shape(bool strided, int* nt, int* pencils_per_tile) {
-  if (strided) {
-    *nt = PassShape<R, L, true>::NT;
-    *pencils_per_tile = 2 * PassShape<R, L, true>::F;
-  } else {
-    *nt = PassShape<R, L, false>::NT;
-    *pencils_per_tile = 2 * PassShape<R, L, false>::F;
+inline void pass_shape(bool strided, int var, int* nt, int* pencils_per_tile) {
+#define RSFDE_SHAPE_CASE(V)                                        \
+  if (var == V) {                                                  \
+    if (strided) {                                                 \
+      *nt = PassShape<R, L, true, V>::NT;                          \
+      *pencils_per_tile = 2 * PassShape<R, L, true, V>::F;         \
+    } else {                                                       \
+      *nt = PassShape<R, L, false, V>::NT;                         \
+      *pencils_per_tile = 2 * PassShape<R, L, false, V>::F;        \
+    }                                                              \
+    return;                                                        \
   }
+  RSFDE_SHAPE_CASE(0)
+  RSFDE_SHAPE_CASE(1)
+  RSFDE_SHAPE_CASE(2)
+#undef RSFDE_SHAPE_CASE
+  *nt = 0;
+  *pencils_per_tile = 0;
 }
 
-#define RSFDE_INSTANTIATE_PASS(R, L)                                                   \
-  template <>                                                                          \
-  hipError_t launch_pass_L<R, L>(const PassArgs& a, bool strided, hipStream_t s) {     \
-    if (strided) {                                                                     \
-      using S = PassShape<R, L, true>;                                                 \
-      hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, true>), dim3((unsigned)a.ntiles), \
-                         dim3(S::NT), 0, s, a);                                        \
-    } else {                                                                           \
-      using S = PassShape<R, L, false>;                                                \
+#define RSFDE_LAUNCH_VARIANT(R, L, V)                                                      \
+  if (var == V) {                                                                          \
+    if (strided) {                                                                         \
+      using S = PassShape<R, L, true, V>;                                                  \
+      hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, true>), dim3((unsigned)a.ntiles),  \
+                         dim3(S::NT), 0, s, a);                                            \
+    } else {                                                                               \
+      using S = PassShape<R, L, false, V>;                                                 \
       hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, false>), dim3((unsigned)a.ntiles), \
-                         dim3(S::NT), 0, s, a);                                        \
-    }                                                                                  \
-    return hipGetLastError();                                                          \
+                         dim3(S::NT), 0, s, a);                                            \
+    }                                                                                      \
+    return hipGetLastError();                                                              \
+  }
+
+#define RSFDE_INSTANTIATE_PASS(R, L)                                                         \
+  template <>                                                                                \
+  hipError_t launch_pass_L<R, L>(const PassArgs& a, bool strided, int var, hipStream_t s) {  \
+    RSFDE_LAUNCH_VARIANT(R, L, 0)                                                            \
+    RSFDE_LAUNCH_VARIANT(R, L, 1)                                                            \
+    RSFDE_LAUNCH_VARIANT(R, L, 2)                                                            \
+    return hipErrorInvalidValue;                                                             \
   }

@@ -21,7 +21,11 @@ k_spectrum(const double* __restrict__ s, int N, const cpx<double>* __restrict__ 
            double* __restrict__ chat64, float* __restrict__ chat32, double* __restrict__ q) {
   constexpr int T = FftPlan<L>::T;
   __shared__ cpx<double> buf[L + 1];
+  __shared__ cpx<double> twl[TwSplit<L>::size];
   const int t = threadIdx.x;
+  twiddle_fill<double, L>(twl, tw, t, T);
+  TwLds<double, L> twp;
+  twp.tab = twl;
   for (int k = t; k < L; k += T) {
     double c = 0.0;
     if (k < N) c = s[k];
@@ -29,7 +33,7 @@ k_spectrum(const double* __restrict__ s, int N, const cpx<double>* __restrict__ 
     buf[k] = cpx<double>{c, 0.0};
   }
   __syncthreads();
-  fft_lds<double, L, -1>(buf, t, tw);
+  fft_lds<double, L, -1>(buf, t, twp);
   for (int k = t; k < L; k += T) {
     const double re = buf[k].x;
     chat64[k] = re / (double)L;

@@ -37,8 +37,10 @@ EXPORTED = (
     "rsfde_workspace_size", "rsfde_setup", "rsfde_set_ebar", "rsfde_step", "rsfde_solve",
     "rsfde_destroy", "rsfde_strerror", "rsfde_set_fields", "rsfde_eval_field", "rsfde_apply_A",
     "rsfde_apply_prec", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
-    "rsfde_get_timing",
+    "rsfde_get_timing", "rsfde_prescan_ebar",
 )
+
+K_CLASSES = ("mv_first", "mv_mid", "mv_last", "dst", "dsd", "dots", "orth_dots", "orth_norm", "update")
 
 
 class rsfde_params(C.Structure):
@@ -105,8 +107,9 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_compute_F.argtypes = [P, I, P, P]
     lib.rsfde_rhs.argtypes = [P, I, P, P, P, P]
     lib.rsfde_get_tables.argtypes = [P, I, I, P, P, P]
-    lib.rsfde_set_timing.argtypes = [P, I]
-    lib.rsfde_get_timing.argtypes = [P, C.POINTER(C.c_longlong), C.POINTER(D), C.POINTER(D)]
+    lib.rsfde_set_timing.argtypes = [P, C.c_uint]
+    lib.rsfde_get_timing.argtypes = [P, I, C.POINTER(C.c_longlong), C.POINTER(D), C.POINTER(D)]
+    lib.rsfde_prescan_ebar.argtypes = [P, I, I]
     for name in EXPORTED:
         getattr(lib, name)
         if name != "rsfde_strerror":
@@ -264,16 +267,23 @@ def rsfde_get_tables(h, instance: int, axis: int, N: int):
     return s, q, lam
 
 
-def rsfde_set_timing(h, enable: bool) -> None:
-    _check(load_library().rsfde_set_timing(h, 1 if enable else 0), "rsfde_set_timing")
+def rsfde_set_timing(h, mask: int) -> None:
+    """mask: bit i enables HIP-event timing of kernel class K_CLASSES[i]; 0 disables."""
+    _check(load_library().rsfde_set_timing(h, int(mask)), "rsfde_set_timing")
 
 
-def rsfde_get_timing(h) -> tuple:
+def rsfde_get_timing(h, kclass: int) -> tuple:
+    """(launches, total ms, total algorithmic bytes) of one kernel class."""
     n = C.c_longlong(0)
     ms = C.c_double(0)
     by = C.c_double(0)
-    _check(load_library().rsfde_get_timing(h, C.byref(n), C.byref(ms), C.byref(by)), "rsfde_get_timing")
+    _check(load_library().rsfde_get_timing(h, int(kclass), C.byref(n), C.byref(ms), C.byref(by)),
+           "rsfde_get_timing")
     return int(n.value), float(ms.value), float(by.value)
+
+
+def rsfde_prescan_ebar(h, instance: int, M: int) -> None:
+    _check(load_library().rsfde_prescan_ebar(h, instance, int(M)), "rsfde_prescan_ebar")
 
 
 class Solver:
