@@ -28,14 +28,25 @@ METRIC = "time-steps/sec (PGMRES to 1e-10) on 2D 1023²; HBM GB/s of FFT/DST ker
 HBM_PEAK_GBS = 8000.0
 KCLASS_NAMES = ("mv_first", "mv_mid", "mv_last", "dst", "dsd", "dots", "orth_dots", "orth_norm", "update")
 KCLASS_KERNELS = {
-    "mv_first": "rsfde_pass_kernel<double, 2048, 1, false> (first-axis operator pass)",
-    "mv_last": "rsfde_pass_kernel<double, 2048, 4, true> (last-axis operator pass + sine transform)",
-    "dst": "rsfde_pass_kernel<double, 2048, 4, true> (sine-transform pass)",
-    "dsd": "rsfde_pass_kernel<double, 2048, 1, false> (transform, 1/mu scaling, transform)",
-    "dots": "k_dots (CGS2 sweep 1)",
-    "orth_dots": "k_orth_dots (CGS2 sweep 2)",
-    "orth_norm": "k_orth_norm_givens (CGS2 sweep 3 + Givens)",
-    "update": "k_update",
+    "mv_first": "rsfde_pass_kernel, first-axis operator pass (B stencil on e.v and v, Toeplitz product)",
+    "mv_mid": "rsfde_pass_kernel, middle-axis operator pass",
+    "mv_last": "rsfde_pass_kernel, last-axis operator pass (B stencil, Toeplitz product, sine transform)",
+    "dst": "rsfde_pass_kernel, sine-transform pass",
+    "dsd": "rsfde_pass_kernel, sine transform + 1/mu scaling + sine transform",
+    "dots": "k_sweep1 (CGS2 sweep 1)",
+    "orth_dots": "k_sweep2 (CGS2 sweep 2)",
+    "orth_norm": "k_sweep3 (CGS2 sweep 3)",
+    "update": "k_update (Givens resolve + solution update)",
+}
+WORKLOAD_TEXT = {
+    "C1": "C1: 1-D N=511, alpha=1.5, kappa=1, e=1+x^2(1+t), manufactured u=e^-t x^2(1-x)^2, "
+          "dt=1/64, GMRES(20) rtol 1e-12, FP64",
+    "C2": "C2: 2-D N=1023x1023, alpha=(1.3,1.7), kappa=(1,0.5), e=2+sin(pi x)sin(pi y)cos t, "
+          "f=8x8 seeded sine modes, psi=0, dt=1/32, GMRES(30) rtol 1e-10, FP64",
+    "C3": "C3: 3-D N=255^3, alpha=(1.2,1.5,1.8), kappa=(1,1,1), e=1+0.5xyz(1+t), manufactured "
+          "u=e^-t prod x_i^2(1-x_i)^2, dt=1/16, GMRES(30) rtol 1e-10, FP64",
+    "C5": "C5: 3-D N=511^3, alpha=(1.4,1.6,1.9), kappa=(1,0.8,0.6), e=2+prod sin(pi x_i) cos t, "
+          "f=8x8x8 seeded sine modes, psi=0, dt=1/8, GMRES(20) rtol 1e-10, FP64",
 }
 
 
@@ -50,9 +61,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kclass: str):
+def read_traffic(workload: str, kclass: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, when it was
-    taken on the current kernel sources; else None."""
+    taken on the current kernel sources and this workload; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -60,7 +71,7 @@ def read_traffic(kclass: str):
         data = json.load(fh)
     if data.get("source_hash") != kernel_source_hash():
         return None
-    ent = data.get("kernels", {}).get(kclass)
+    ent = data.get("workloads", {}).get(workload, {}).get(kclass)
     return None if ent is None else ent.get("bytes_per_launch")
 
 
@@ -144,6 +155,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--workload", default="C2", choices=("C1", "C2", "C3", "C5"))
+    ap.add_argument("--timing-every", type=int, default=4,
+                    help="time one launch in this many of the dominant kernel class")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded design is "
@@ -155,12 +171,22 @@ def main():
     from rsfde_workloads import config
 
     torch.cuda.set_device(0)
-    inst = config("C2")
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8,
+                          "launches": 3}), flush=True)
+        return
+    inst = config(args.workload)
     K, W = args.steps, args.warmup
 
     # ---- FP64 form: warm-up with every kernel class timed (to find the dominant one)
     g = Stepper(inst)
-    R.rsfde_set_timing(g.S.h, (1 << len(KCLASS_NAMES)) - 1)
+    R.rsfde_set_timing(g.S.h, (1 << len(KCLASS_NAMES)) - 1, 1)
     for _ in range(W):
         g.step()
     tot = {}
@@ -169,8 +195,8 @@ def main():
         tot[name] = (n, ms, by)
     dom = max(tot, key=lambda k: tot[k][1])
     dom_cls = KCLASS_NAMES.index(dom)
-    # ---- timed region: time only the dominant class
-    R.rsfde_set_timing(g.S.h, 1 << dom_cls)
+    # ---- timed region: time one launch in `timing_every` of the dominant class
+    R.rsfde_set_timing(g.S.h, 1 << dom_cls, args.timing_every)
     it0 = g.iters
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -179,14 +205,14 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n, ms, by = R.rsfde_get_timing(g.S.h, dom_cls)
-    R.rsfde_set_timing(g.S.h, 0)
+    R.rsfde_set_timing(g.S.h, 0, 1)
     elapsed = t1 - t0
     iters = g.iters - it0
     u64 = g.u.clone()
     status = g.status
     g.close()
     achieved = (by / n) / ((ms / n) * 1e-3) / 1e9 if n else 0.0
-    traffic = read_traffic(dom)
+    traffic = read_traffic(args.workload, dom)
     out = {
         "metric": METRIC,
         "value": K / elapsed,
@@ -200,9 +226,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "C2: 2-D N=1023x1023, alpha=(1.3,1.7), kappa=(1,0.5), "
-                               "e=2+sin(pi x)sin(pi y)cos t, f=8x8 seeded sine modes, psi=0, "
-                               "dt=1/32, GMRES(30) rtol 1e-10, FP64",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "unknowns": inst.size, "gmres_iters_per_step": iters / K,
                    "status": status},
         "roofline": {

@@ -221,12 +221,13 @@ int rsfde_prescan_ebar(rsfde_handle h, int instance, int M);
 #define RSFDE_K_UPDATE      8  /* solution update */
 #define RSFDE_K_NCLASS      9
 
-/* Record HIP events around every launch of the kernel classes in `mask` (on the
- * handle's stream) and reset the counters; mask 0 switches timing off.
- * rsfde_get_timing returns, for one class, the launches timed since then, their
- * summed milliseconds and their summed algorithmic HBM bytes (arrays read plus
- * arrays written, each counted once). */
-int rsfde_set_timing(rsfde_handle h, unsigned mask);
+/* Stamp HIP events at the start and end of one launch in every `every` (>= 1)
+ * of each kernel class in `mask` (on the handle's stream) and reset the
+ * counters; mask 0 switches timing off.  rsfde_get_timing returns, for one
+ * class, the launches timed since then, their summed milliseconds and their
+ * summed algorithmic HBM bytes (arrays read plus arrays written, each counted
+ * once). */
+int rsfde_set_timing(rsfde_handle h, unsigned mask, int every);
 int rsfde_get_timing(rsfde_handle h, int kclass, long long* launches, double* ms, double* bytes);
 
 #ifdef __cplusplus

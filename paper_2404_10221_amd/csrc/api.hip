@@ -20,9 +20,11 @@
 // ---------------------------------------------------------------------------
 #define RSFDE_DECL(L)                                                                        \
   template <>                                                                                \
-  hipError_t launch_pass_L<double, L>(const PassArgs&, bool, int, hipStream_t);             \
+  hipError_t launch_pass_L<double, L>(const PassArgs&, bool, int, hipStream_t, hipEvent_t,  \
+                                      hipEvent_t);                                           \
   template <>                                                                                \
-  hipError_t launch_pass_L<float, L>(const PassArgs&, bool, int, hipStream_t);              \
+  hipError_t launch_pass_L<float, L>(const PassArgs&, bool, int, hipStream_t, hipEvent_t,   \
+                                     hipEvent_t);                                            \
   template <>                                                                                \
   hipError_t launch_spectrum_L<L>(const double*, int, const cpx<double>*, double*, float*,  \
                                   double*, hipStream_t);
@@ -40,12 +42,13 @@ static bool supported_L(int L) {
   }
 }
 
-static hipError_t launch_pass(int L, bool fp32, const PassArgs& a, bool strided, hipStream_t s) {
+static hipError_t launch_pass(int L, bool fp32, const PassArgs& a, bool strided, hipStream_t s,
+                              hipEvent_t ea = nullptr, hipEvent_t eb = nullptr) {
   switch (L) {
 #define RSFDE_CASE(LL)                                                    \
   case LL:                                                                \
-    return fp32 ? launch_pass_L<float, LL>(a, strided, a.var, s)          \
-                : launch_pass_L<double, LL>(a, strided, a.var, s);
+    return fp32 ? launch_pass_L<float, LL>(a, strided, a.var, s, ea, eb)  \
+                : launch_pass_L<double, LL>(a, strided, a.var, s, ea, eb);
     RSFDE_FOR_EACH_L(RSFDE_CASE)
 #undef RSFDE_CASE
   }
@@ -160,6 +163,8 @@ struct rsfde_ctx {
   hipStream_t stream = nullptr;
   GmresSummary* pinned = nullptr;
   unsigned tmask = 0;
+  int tevery = 1;
+  long long tseen[RSFDE_K_NCLASS] = {0};
   std::vector<TimedPass> pending;
   std::vector<hipEvent_t> ev_free;
   long long t_launches[RSFDE_K_NCLASS] = {0};
@@ -175,19 +180,18 @@ static hipError_t get_event(rsfde_ctx* h, hipEvent_t* ev) {
   return hipEventCreate(ev);
 }
 
-// Launch `fn` (returning hipError_t); when class `cls` is timed, bracket it by events.
+// Launch `fn(ea, eb)` (returning hipError_t); when class `cls` is timed, the
+// dispatch itself stamps the events (no extra stream commands).
 template <typename Fn>
 static int timed_launch(rsfde_ctx* h, int cls, double bytes, Fn fn) {
-  if ((h->tmask >> cls) & 1u) {
+  if (((h->tmask >> cls) & 1u) && (h->tseen[cls]++ % h->tevery) == 0) {
     hipEvent_t ea, eb;
     CK(get_event(h, &ea));
     CK(get_event(h, &eb));
-    CK(hipEventRecord(ea, h->stream));
-    CK(fn());
-    CK(hipEventRecord(eb, h->stream));
+    CK(fn(ea, eb));
     h->pending.push_back(TimedPass{ea, eb, bytes, cls});
   } else {
-    CK(fn());
+    CK(fn(nullptr, nullptr));
   }
   return RSFDE_OK;
 }
@@ -307,9 +311,13 @@ static PassArgs mk_pass(const Inst& I, int axis, int op, bool fp32) {
   if (axis == 0) {
     a.tiles_inner = 1;
     a.ntiles = (a.npencil + ppt - 1) / ppt;
+    a.xcd_remap = 0;
+    a.nlaunch = a.ntiles;
   } else {
     a.tiles_inner = (inner + ppt - 1) / ppt;
     a.ntiles = (a.npencil / inner) * a.tiles_inner;
+    a.xcd_remap = 1;
+    a.nlaunch = (a.ntiles + 7) / 8 * 8;
   }
   a.bd = 1.0 - A.alpha / 12.0;
   a.bo = A.alpha / 24.0;
@@ -361,9 +369,10 @@ static int op_class(int op) {
 static int run_pass(rsfde_ctx* h, const Inst& I, const PassArgs& a, bool fp32) {
   const int L = I.ax[a.axis].L;
   if (a.ntiles <= 0) return RSFDE_OK;
-  if (a.ntiles > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
-  return timed_launch(h, op_class(a.op), pass_bytes(a, I, fp32),
-                      [&]() { return launch_pass(L, fp32, a, a.axis > 0, h->stream); });
+  if (a.nlaunch > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
+  return timed_launch(h, op_class(a.op), pass_bytes(a, I, fp32), [&](hipEvent_t ea, hipEvent_t eb) {
+    return launch_pass(L, fp32, a, a.axis > 0, h->stream, ea, eb);
+  });
 }
 
 static int flush_timing(rsfde_ctx* h) {
@@ -622,9 +631,12 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
       ka.j = jj;
       ka.m = m;
       const double vb = 8.0 * (double)I.n;
-      CKS(timed_launch(h, RSFDE_K_DOTS, vb * (jj + 2), [&]() { return kry_sweep(1, ka, h->stream); }));
-      CKS(timed_launch(h, RSFDE_K_ORTH_DOTS, vb * (jj + 3), [&]() { return kry_sweep(2, ka, h->stream); }));
-      CKS(timed_launch(h, RSFDE_K_ORTH_NORM, vb * (jj + 3), [&]() { return kry_sweep(3, ka, h->stream); }));
+      CKS(timed_launch(h, RSFDE_K_DOTS, vb * (jj + 2),
+                       [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(1, ka, h->stream, ea, eb); }));
+      CKS(timed_launch(h, RSFDE_K_ORTH_DOTS, vb * (jj + 3),
+                       [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(2, ka, h->stream, ea, eb); }));
+      CKS(timed_launch(h, RSFDE_K_ORTH_NORM, vb * (jj + 3),
+                       [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(3, ka, h->stream, ea, eb); }));
     }
     GmRes gu;
     gu.st = I.st;
@@ -633,7 +645,9 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
     gu.j = jend - 1;
     gu.pend = jend - 1;
     gu.m = m;
-    CKS(timed_launch(h, RSFDE_K_UPDATE, 0.0, [&]() { return kry_update(I.V, I.ldv, I.n, x, gu, h->stream); }));
+    CKS(timed_launch(h, RSFDE_K_UPDATE, 0.0, [&](hipEvent_t ea, hipEvent_t eb) {
+      return kry_update(I.V, I.ldv, I.n, x, gu, h->stream, ea, eb);
+    }));
     CKS(read_summary(h, I, S));
     if (S->flag != GM_RUNNING) return RSFDE_OK;
     j = jend;
@@ -1121,12 +1135,14 @@ int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* 
   return RSFDE_OK;
 }
 
-int rsfde_set_timing(rsfde_handle h, unsigned mask) {
-  if (!h) return RSFDE_E_INVALID_ARG;
+int rsfde_set_timing(rsfde_handle h, unsigned mask, int every) {
+  if (!h || every < 1) return RSFDE_E_INVALID_ARG;
   CK(hipStreamSynchronize(h->stream));
   CKS(flush_timing(h));
   h->tmask = mask;
+  h->tevery = every;
   for (int c = 0; c < RSFDE_K_NCLASS; ++c) {
+    h->tseen[c] = 0;
     h->t_launches[c] = 0;
     h->t_ms[c] = 0;
     h->t_bytes[c] = 0;

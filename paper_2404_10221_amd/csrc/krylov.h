@@ -205,7 +205,9 @@ struct KryArgs {
 // Launchers (krylov.hip)
 hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial, int first,
                           double rtol, double inner_rtol, int mixed, int m, hipStream_t s);
-hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s);  // which = 1, 2, 3
+// ea/eb: when non-null, HIP events stamped at the dispatch's start and end
+hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea = nullptr,
+                     hipEvent_t eb = nullptr);  // which = 1, 2, 3
 hipError_t kry_update(const double* V, int64_t ldv, int64_t n, double* x, const GmRes& g,
-                      hipStream_t s);
+                      hipStream_t s, hipEvent_t ea = nullptr, hipEvent_t eb = nullptr);
 hipError_t kry_state_reset(GmresState* st, hipStream_t s);

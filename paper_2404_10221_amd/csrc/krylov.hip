@@ -4,6 +4,7 @@
 // cross-block synchronisation).  The next sweep adds those partials in a fixed
 // order in its prologue (every block redundantly; the sum is deterministic),
 // so no single-block finish kernel sits between sweeps.
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "krylov.h"
@@ -290,15 +291,15 @@ hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial
   return hipGetLastError();
 }
 
-#define KRY_SWEEP(KERNEL, nv, g, a, s)                                                         \
-  do {                                                                                         \
-    if ((nv) <= 8) hipLaunchKernelGGL(KERNEL<8>, g, dim3(SweepNT<8>::value), 0, s, a);         \
-    else if ((nv) <= 16) hipLaunchKernelGGL(KERNEL<16>, g, dim3(SweepNT<16>::value), 0, s, a); \
-    else if ((nv) <= 32) hipLaunchKernelGGL(KERNEL<32>, g, dim3(SweepNT<32>::value), 0, s, a); \
-    else hipLaunchKernelGGL(KERNEL<64>, g, dim3(SweepNT<64>::value), 0, s, a);                 \
+#define KRY_SWEEP(KERNEL, nv, g, a, s)                                                          \
+  do {                                                                                          \
+    if ((nv) <= 8) hipExtLaunchKernelGGL(KERNEL<8>, g, dim3(SweepNT<8>::value), 0, s, ea, eb, 0, a); \
+    else if ((nv) <= 16) hipExtLaunchKernelGGL(KERNEL<16>, g, dim3(SweepNT<16>::value), 0, s, ea, eb, 0, a); \
+    else if ((nv) <= 32) hipExtLaunchKernelGGL(KERNEL<32>, g, dim3(SweepNT<32>::value), 0, s, ea, eb, 0, a); \
+    else hipExtLaunchKernelGGL(KERNEL<64>, g, dim3(SweepNT<64>::value), 0, s, ea, eb, 0, a);    \
   } while (0)
 
-hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s) {
+hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
   const int nv = a.j + 1;
   const dim3 g(kry_blocks(a.n));
   if (which == 1) KRY_SWEEP(k_sweep1, nv, g, a, s);
@@ -308,11 +309,11 @@ hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s) {
 }
 
 hipError_t kry_update(const double* V, int64_t ldv, int64_t n, double* x, const GmRes& g,
-                      hipStream_t s) {
+                      hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
   int64_t nb = (n / 2 + 1023) / 1024;
   if (nb > 1024) nb = 1024;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_update, dim3((unsigned)nb), dim3(256), 0, s, V, ldv, n, x, g);
+  hipExtLaunchKernelGGL(k_update, dim3((unsigned)nb), dim3(256), 0, s, ea, eb, 0, V, ldv, n, x, g);
   return hipGetLastError();
 }
 

@@ -12,6 +12,8 @@
 // matvec A v = B_alpha E v + S_alpha v and the preconditioner solve are chains of
 // such passes (one sweep per axis and per transform direction).
 #pragma once
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "common.h"
@@ -34,7 +36,9 @@ struct PassArgs {
   int64_t inner;         // element stride of the pass axis (prod of N_l, l < axis)
   int64_t npencil;       // pencils in the pass (= n / N)
   int64_t tiles_inner;   // strided passes: tiles across the inner index range
-  int64_t ntiles;        // workgroups launched
+  int64_t ntiles;        // tiles (pencil groups) in the pass
+  int64_t nlaunch;       // workgroups launched (>= ntiles)
+  int xcd_remap;         // 1: block b takes tile (b mod 8) * ceil(ntiles/8) + b/8
   const void* in_c;      // Toeplitz / transform input (v for the first pass)
   const void* in_a;      // stencil input (e for the first pass)
   const double* in_x;    // MV_LAST: additive FP64 vector (b or F), may be NULL
@@ -129,8 +133,15 @@ rsfde_pass_kernel(const PassArgs a) {
   const bool in64 = (a.flags & FL_IN64) != 0;
   const bool out64 = (a.flags & FL_OUT64) != 0;
 
-  // ---- tile geometry
-  const int64_t tile = blockIdx.x;
+  // ---- tile geometry.  Blocks are dispatched round-robin over the 8 XCDs
+  // (each with its own L2); for strided passes every XCD takes a contiguous run
+  // of tiles, so neighbouring tiles (which share cache lines) meet in one L2.
+  int64_t tile = blockIdx.x;
+  if (a.xcd_remap) {
+    const int64_t b = blockIdx.x, tpx = (a.ntiles + 7) >> 3;
+    tile = (b & 7) * tpx + (b >> 3);
+    if (tile >= a.ntiles) return;
+  }
   int64_t row0 = 0, gbase = 0;
   int nvalid;
   if constexpr (!STRIDED) {
@@ -471,8 +482,10 @@ rsfde_pass_kernel(const PassArgs a) {
 
 // Host launcher for one (precision, length); defined in the per-length
 // instantiation units.  Returns a hipError_t.
+// ea/eb: when non-null, HIP events stamped at the dispatch's start and end.
 template <typename R, int L>
-hipError_t launch_pass_L(const PassArgs& a, bool strided, int var, hipStream_t s);
+hipError_t launch_pass_L(const PassArgs& a, bool strided, int var, hipStream_t s, hipEvent_t ea,
+                         hipEvent_t eb);
 
 // Workgroup shape of a variant (threads, pencils per tile).
 template <typename R, int L>
@@ -496,23 +509,28 @@ inline void pass_shape(bool strided, int var, int* nt, int* pencils_per_tile) {
   *pencils_per_tile = 0;
 }
 
-#define RSFDE_LAUNCH_VARIANT(R, L, V)                                                      \
-  if (var == V) {                                                                          \
-    if (strided) {                                                                         \
-      using S = PassShape<R, L, true, V>;                                                  \
-      hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, true>), dim3((unsigned)a.ntiles),  \
-                         dim3(S::NT), 0, s, a);                                            \
-    } else {                                                                               \
-      using S = PassShape<R, L, false, V>;                                                 \
-      hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, false>), dim3((unsigned)a.ntiles), \
-                         dim3(S::NT), 0, s, a);                                            \
-    }                                                                                      \
-    return hipGetLastError();                                                              \
+#define RSFDE_LAUNCH_VARIANT(R, L, V)                                                           \
+  if (var == V) {                                                                               \
+    if (strided) {                                                                              \
+      using S = PassShape<R, L, true, V>;                                                       \
+      if (ea) hipExtLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, true>),                      \
+                                    dim3((unsigned)a.nlaunch), dim3(S::NT), 0, s, ea, eb, 0, a); \
+      else hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, true>), dim3((unsigned)a.nlaunch), \
+                              dim3(S::NT), 0, s, a);                                            \
+    } else {                                                                                    \
+      using S = PassShape<R, L, false, V>;                                                      \
+      if (ea) hipExtLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, false>),                     \
+                                    dim3((unsigned)a.nlaunch), dim3(S::NT), 0, s, ea, eb, 0, a); \
+      else hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, false>), dim3((unsigned)a.nlaunch), \
+                              dim3(S::NT), 0, s, a);                                            \
+    }                                                                                           \
+    return hipGetLastError();                                                                   \
   }
 
 #define RSFDE_INSTANTIATE_PASS(R, L)                                                         \
   template <>                                                                                \
-  hipError_t launch_pass_L<R, L>(const PassArgs& a, bool strided, int var, hipStream_t s) {  \
+  hipError_t launch_pass_L<R, L>(const PassArgs& a, bool strided, int var, hipStream_t s,   \
+                                 hipEvent_t ea, hipEvent_t eb) {                           \
     RSFDE_LAUNCH_VARIANT(R, L, 0)                                                            \
     RSFDE_LAUNCH_VARIANT(R, L, 1)                                                            \
     RSFDE_LAUNCH_VARIANT(R, L, 2)                                                            \

@@ -107,7 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_compute_F.argtypes = [P, I, P, P]
     lib.rsfde_rhs.argtypes = [P, I, P, P, P, P]
     lib.rsfde_get_tables.argtypes = [P, I, I, P, P, P]
-    lib.rsfde_set_timing.argtypes = [P, C.c_uint]
+    lib.rsfde_set_timing.argtypes = [P, C.c_uint, I]
     lib.rsfde_get_timing.argtypes = [P, I, C.POINTER(C.c_longlong), C.POINTER(D), C.POINTER(D)]
     lib.rsfde_prescan_ebar.argtypes = [P, I, I]
     for name in EXPORTED:
@@ -267,9 +267,10 @@ def rsfde_get_tables(h, instance: int, axis: int, N: int):
     return s, q, lam
 
 
-def rsfde_set_timing(h, mask: int) -> None:
-    """mask: bit i enables HIP-event timing of kernel class K_CLASSES[i]; 0 disables."""
-    _check(load_library().rsfde_set_timing(h, int(mask)), "rsfde_set_timing")
+def rsfde_set_timing(h, mask: int, every: int = 1) -> None:
+    """mask: bit i enables HIP-event timing of kernel class K_CLASSES[i] (one launch in
+    `every`); 0 disables."""
+    _check(load_library().rsfde_set_timing(h, int(mask), int(every)), "rsfde_set_timing")
 
 
 def rsfde_get_timing(h, kclass: int) -> tuple:
