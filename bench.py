@@ -162,8 +162,8 @@ def main():
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded design is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
