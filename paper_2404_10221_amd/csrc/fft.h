@@ -47,6 +47,24 @@ RSFDE_PLAN(4096, 16, 16, 16, 16)
 
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 
+// One transform's sequence in LDS, with one pad slot after every 256 bytes.
+// The LDS of gfx950 serves 256 bytes (64 four-byte banks) per pass; the
+// Stockham writes of the early stages step through a sequence with strides of R
+// elements, which lands a whole wavefront on a few banks.  The pad shifts each
+// 256-byte row by one element, spreading those writes over every bank, while
+// runs of consecutive elements stay conflict-free.  The layout also keeps the
+// per-element offsets of a butterfly compile-time constants (see fft_stage).
+template <typename R, int L>
+struct LdsSeq {
+  static constexpr int BS = 256 / (int)sizeof(cpx<R>);  // elements per 256-byte row
+  static constexpr int size = L + L / BS;                // slots of one sequence
+  cpx<R>* p;
+  __device__ __forceinline__ static constexpr int pos(int i) { return i + i / BS; }
+  __device__ __forceinline__ cpx<R>& operator[](int i) const { return p[pos(i)]; }
+  // R-typed view of component c of element i
+  __device__ __forceinline__ R& comp(int i, int c) const { return ((R*)(p + pos(i)))[c]; }
+};
+
 // Twiddles W_L^m = W_L^{m mod B} * W_L^{B floor(m/B)}: two short tables kept in
 // LDS (B + L/B entries) replace the length-L table in global memory.
 template <int L> struct TwSplit {
@@ -240,18 +258,30 @@ __device__ __forceinline__ void dft(cpx<R>* v) {
 // One Stockham stage on the thread's part of one transform held in LDS;
 // twl is the LDS twiddle table filled by twiddle_fill.
 template <typename R, int L, int DIR, int S, typename TW>
-__device__ __forceinline__ void fft_stage(cpx<R>* __restrict__ buf, int t, const TW& tw) {
+__device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const TW& tw) {
   using P = FftPlan<L>;
   constexpr int RAD = P::R[S];
   constexpr int Ns = StageNs<L, S>::value;
   constexpr int T = P::T, E = P::E, NB = E / RAD, LR = L / RAD;
   static_assert(E % RAD == 0, "radix must divide the per-thread element count");
   cpx<R> v[E];
+  using Q = LdsSeq<R, L>;
+  constexpr int BS = Q::BS;
+  // Reads x[j + r L/R]: when L/R is a whole number of rows, pos(j + r L/R) =
+  // pos(j) + r (L/R + L/(R BS)), a constant offset per r.
+  constexpr bool rd_fold = LR % BS == 0;
+  // Writes y[base + r Ns], base = (j/Ns) Ns R + j mod Ns: the row of base + r Ns
+  // is the row of base plus (r Ns)/BS when Ns is a multiple of BS, or Ns divides
+  // BS and Ns R is a multiple or a divisor of BS (no carry out of the row).
+  constexpr bool wr_fold =
+      Ns % BS == 0 || (BS % Ns == 0 && ((Ns * RAD) % BS == 0 || BS % (Ns * RAD) == 0));
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = t + b * T;
+    const int pj = Q::pos(j);
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) v[b * RAD + r] = buf[j + r * LR];
+    for (int r = 0; r < RAD; ++r)
+      v[b * RAD + r] = rd_fold ? buf.p[pj + r * (LR + LR / BS)] : buf[j + r * LR];
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -274,14 +304,18 @@ __device__ __forceinline__ void fft_stage(cpx<R>* __restrict__ buf, int t, const
     const int j = t + b * T;
     const int k = j % Ns;
     const int base = (j / Ns) * Ns * RAD + k;
+    const int pb = Q::pos(base);
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) buf[base + r * Ns] = v[b * RAD + r];
+    for (int r = 0; r < RAD; ++r) {
+      if constexpr (wr_fold) buf.p[pb + r * Ns + (r * Ns) / BS] = v[b * RAD + r];
+      else buf[base + r * Ns] = v[b * RAD + r];
+    }
   }
   __syncthreads();
 }
 
 template <typename R, int L, int DIR, int S, typename TW>
-__device__ __forceinline__ void fft_stages(cpx<R>* buf, int t, const TW& tw) {
+__device__ __forceinline__ void fft_stages(const LdsSeq<R, L> buf, int t, const TW& tw) {
   if constexpr (S < FftPlan<L>::NS) {
     fft_stage<R, L, DIR, S>(buf, t, tw);
     fft_stages<R, L, DIR, S + 1>(buf, t, tw);
@@ -292,6 +326,6 @@ __device__ __forceinline__ void fft_stages(cpx<R>* buf, int t, const TW& tw) {
 // workgroup must call it together: it contains barriers).  `tw` is a TwReg or
 // TwLds twiddle provider.
 template <typename R, int L, int DIR, typename TW>
-__device__ __forceinline__ void fft_lds(cpx<R>* buf, int t, const TW& tw) {
+__device__ __forceinline__ void fft_lds(const LdsSeq<R, L> buf, int t, const TW& tw) {
   fft_stages<R, L, DIR, 0>(buf, t, tw);
 }

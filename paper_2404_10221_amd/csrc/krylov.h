@@ -104,6 +104,7 @@ __device__ __forceinline__ double gm_block_sum(double x, double* sh /* >= 16 */)
 // and, when this kernel resolved a finishing step and want_y, y[0..k) is in ysh.
 __device__ __forceinline__ void gm_prologue(const GmRes& g, GmOut* o, double* ysh, bool want_y) {
   __shared__ double sh[16];
+  __shared__ double hc[RSFDE_MAX_RESTART + 1];  // Hessenberg column (LDS, not private memory)
   GmresState* st = g.st;
   const bool cand = g.pend >= 0;
   const int fl_prev = st->FL[cand ? g.pend : g.j];
@@ -130,7 +131,6 @@ __device__ __forceinline__ void gm_prologue(const GmRes& g, GmOut* o, double* ys
       const int j = g.pend;
       const int MX = RSFDE_MAX_RESTART;
       const bool writer = blockIdx.x == 0;
-      double hc[RSFDE_MAX_RESTART + 1];
       for (int i = 0; i <= j; ++i) hc[i] = st->h[i] + st->h2[i];
       const double hn = sqrt(nu);
       double hsz = 0.0;

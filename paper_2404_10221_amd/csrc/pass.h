@@ -96,8 +96,11 @@ __device__ __forceinline__ void set_comp(cpx<R>& z, int c, R v) {
 template <typename R, int L, bool STRIDED, int VAR>
 struct PassShape {
   static constexpr int T = FftPlan<L>::T;
-  static constexpr int bytes_per_fft = (L + 1) * (int)sizeof(cpx<R>);
-  static constexpr int cap = 160 * 1024 - TwSplit<L>::size * (int)sizeof(cpx<R>) - L * (int)sizeof(R);
+  static constexpr int bytes_per_fft = (LdsSeq<R, L>::size + 4) * (int)sizeof(cpx<R>);
+  // LDS left for the transforms: 160 KB minus twiddles, the circulant spectrum
+  // and 2 KB for the small shared arrays (block sums, Givens column, y)
+  static constexpr int cap =
+      160 * 1024 - TwSplit<L>::size * (int)sizeof(cpx<R>) - L * (int)sizeof(R) - 2048;
   static constexpr int want = 512 / T > 1 ? 512 / T : 1;
   static constexpr int lim = cap / bytes_per_fft;
   static constexpr int F0a = want < lim ? want : lim;
@@ -107,11 +110,15 @@ struct PassShape {
   static constexpr int NT = F * T;
 };
 
+// Register budget of 128 VGPRs (4 waves per SIMD): measured faster on HBM-bound
+// grids than the unconstrained allocation (3 waves per SIMD) despite a few spills.
 template <typename R, int L, int F, bool STRIDED>
-__global__ void __launch_bounds__(F * FftPlan<L>::T)
+__global__ void __launch_bounds__(F * FftPlan<L>::T) __attribute__((amdgpu_waves_per_eu(4)))
 rsfde_pass_kernel(const PassArgs a) {
   using P = FftPlan<L>;
-  constexpr int T = P::T, E = P::E, NT = F * T, LP = L + 1, PT = 2 * F;
+  constexpr int T = P::T, E = P::E, NT = F * T, PT = 2 * F;
+  // sequences 64 bytes apart modulo 256 (strided tiles spread over the banks)
+  constexpr int LP = LdsSeq<R, L>::size + 4;
   constexpr int NE = STRIDED ? E : E / 2;  // element slots per thread
   __shared__ cpx<R> lds[F * LP];
   __shared__ cpx<R> twl[TwUseReg<L>::value ? 1 : TwSplit<L>::size];
@@ -128,7 +135,7 @@ rsfde_pass_kernel(const PassArgs a) {
   }
   const int f = tid / T;
   const int t = tid - f * T;
-  cpx<R>* buf = lds + f * LP;
+  const LdsSeq<R, L> buf{lds + f * LP};
   const int N = a.N;
   const bool in64 = (a.flags & FL_IN64) != 0;
   const bool out64 = (a.flags & FL_OUT64) != 0;
@@ -230,7 +237,7 @@ rsfde_pass_kernel(const PassArgs a) {
           R c = v ? ld_any<R>(a.in_c, g, in64) * sc : (R)0;
           R av = v ? ld_any<R>(a.in_a, g, false) : (R)0;
           if (ev_mode) av *= c;
-          cpx<R>* bb = lds + (pp >> 1) * LP;
+          LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           set_comp(bb[p], pp & 1, c);
           set_comp(bb[N + 1 + p], pp & 1, av);
         }
@@ -263,7 +270,7 @@ rsfde_pass_kernel(const PassArgs a) {
         s_pos(i, p, pp);
         if (p < N) {
           const int c = pp & 1;
-          const cpx<R>* bb = lds + (pp >> 1) * LP;
+          const LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           R cm = p > 0 ? comp_of(bb[p - 1], c) : (R)0;
           R bc = comp_of(bb[p], c) * bd + (cm + comp_of(bb[p + 1], c)) * bo;
           R ba = comp_of(bb[N + 1 + p], c) * bd + (comp_of(bb[N + p], c) + comp_of(bb[N + 2 + p], c)) * bo;
@@ -316,7 +323,7 @@ rsfde_pass_kernel(const PassArgs a) {
         s_pos(i, p, pp);
         if (p < N) {
           const int c = pp & 1;
-          const cpx<R>* bb = lds + (pp >> 1) * LP;
+          const LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           const int64_t g = gbase + (int64_t)p * inner + pp;
           const bool v = pp < nvalid;
           R w = rs[i] + comp_of(bb[p], c) * eta;
@@ -356,7 +363,7 @@ rsfde_pass_kernel(const PassArgs a) {
         int p, pp;
         s_pos(i, p, pp);
         if (p < N) {
-          cpx<R>* bb = lds + (pp >> 1) * LP;
+          LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           set_comp(bb[p + 1], pp & 1, rs[i]);
           set_comp(bb[L - 1 - p], pp & 1, -rs[i]);
         }
@@ -391,7 +398,7 @@ rsfde_pass_kernel(const PassArgs a) {
         if (p < N) {
           const bool v = pp < nvalid;
           R x = v ? ld_any<R>(a.in_c, gbase + (int64_t)p * inner + pp, in64) : (R)0;
-          cpx<R>* bb = lds + (pp >> 1) * LP;
+          LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           set_comp(bb[p + 1], pp & 1, x);
           set_comp(bb[L - 1 - p], pp & 1, -x);
         }
@@ -472,9 +479,10 @@ rsfde_pass_kernel(const PassArgs a) {
       int p, pp;
       s_pos(i, p, pp);
       if (p < N && pp < nvalid) {
-        const cpx<R>* bb = lds + (pp >> 1) * LP;
-        const cpx<R> Z = bb[p + 1];
-        st_any<R>(a.out_a, gbase + (int64_t)p * inner + pp, (pp & 1) ? Z.x : -Z.y, out64);
+        const LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
+        // component pp&1 of the packed transform: -Im for the first pencil, Re for the second
+        const R z = bb.comp(p + 1, (pp & 1) ^ 1);
+        st_any<R>(a.out_a, gbase + (int64_t)p * inner + pp, (pp & 1) ? z : -z, out64);
       }
     }
   }

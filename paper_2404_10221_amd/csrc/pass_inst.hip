@@ -20,7 +20,8 @@ __global__ void __launch_bounds__(FftPlan<L>::T)
 k_spectrum(const double* __restrict__ s, int N, const cpx<double>* __restrict__ tw,
            double* __restrict__ chat64, float* __restrict__ chat32, double* __restrict__ q) {
   constexpr int T = FftPlan<L>::T;
-  __shared__ cpx<double> buf[L + 1];
+  __shared__ cpx<double> bufs[LdsSeq<double, L>::size];
+  const LdsSeq<double, L> buf{bufs};
   __shared__ cpx<double> twl[TwSplit<L>::size];
   const int t = threadIdx.x;
   twiddle_fill<double, L>(twl, tw, t, T);
