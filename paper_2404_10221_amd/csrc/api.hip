@@ -131,7 +131,8 @@ struct Inst {
   double* fsin_e[3] = {nullptr, nullptr, nullptr};
   double* fsin_f[3] = {nullptr, nullptr, nullptr};
   int k_prev = 4;
-  int var[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // tile variant per axis and precision
+  int var[3][2][2] = {};  // tile variant per axis, precision (FP64, FP32) and pass class
+                          // (0: operator passes, 1: transform passes)
 };
 
 struct TimedPass {
@@ -306,7 +307,7 @@ static PassArgs mk_pass(const Inst& I, int axis, int op, bool fp32) {
   a.inner = inner;
   a.npencil = I.n / A.N;
   int nt, ppt;
-  a.var = I.var[axis][fp32 ? 1 : 0];
+  a.var = I.var[axis][fp32 ? 1 : 0][op <= OP_MV_LAST ? 0 : 1];
   pass_shape_rt(A.L, fp32, axis > 0, a.var, &nt, &ppt);
   if (axis == 0) {
     a.tiles_inner = 1;
@@ -722,47 +723,83 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
 }
 
 // ---------------------------------------------------------------------------
-// tile autotuner: time the workgroup-shape variants of a transform pass on each
-// axis (and precision) and keep the fastest.  Results do not depend on the
-// variant (pencil pairing and arithmetic are the same), only the speed does.
-// ---------------------------------------------------------------------------
+// tile autotuner: time the workgroup-shape variants of every pass kind the
+// chains use (operator pass and transform pass, per axis and precision) on the
+// instance's own grid and keep the fastest.  The variants only change how many
+// pencils a workgroup holds; the arithmetic per pencil is the same, so the
+// choice never changes results.  RSFDE_NO_AUTOTUNE=1 keeps variant 0.
 static int autotune(rsfde_ctx* h, Inst& I) {
   const char* off = getenv("RSFDE_NO_AUTOTUNE");
   if (off && off[0] == '1') return RSFDE_OK;
-  CK(fill_f64((double*)I.tmp[0], I.n, 0.0, h->stream));
+  const char* vb = getenv("RSFDE_AUTOTUNE_VERBOSE");
+  const bool verbose = vb && vb[0] == '1';
+  for (int k = 0; k < 4; ++k) CK(fill_f64((double*)I.tmp[k], I.n, 0.0, h->stream));
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
   const int nprec = I.p.precision == RSFDE_MIXED ? 2 : 1;
+  const int d = I.d;
   int status = RSFDE_OK;
-  for (int ax = 0; ax < I.d && status == RSFDE_OK; ++ax) {
+  for (int ax = 0; ax < d && status == RSFDE_OK; ++ax) {
     for (int fp = 0; fp < nprec && status == RSFDE_OK; ++fp) {
-      float best = 1e30f;
-      int bestv = 0;
-      for (int v = 0; v < RSFDE_PASS_VARIANTS; ++v) {
-        I.var[ax][fp] = v;
-        PassArgs t = mk_pass(I, ax, OP_DST, fp == 1);
-        t.in_c = I.tmp[0];
-        t.out_a = I.tmp[1];
+      for (int cls = 0; cls < 2 && status == RSFDE_OK; ++cls) {
+        if (cls == 1 && d == 1) continue;  // one-axis chains have no transform pass
+        int op, flags = 0;
+        if (cls == 1) {
+          op = ax == 0 ? OP_DSD : OP_DST;
+        } else if (d == 1) {
+          op = OP_MV_LAST;
+          flags = FL_FIRST_IS_LAST | FL_IN64 | FL_OUT64 | FL_PREC_FULL;
+        } else if (ax == 0) {
+          op = OP_MV_FIRST;
+          flags = FL_IN64;
+        } else if (ax < d - 1) {
+          op = OP_MV_MID;
+        } else {
+          op = OP_MV_LAST;
+          flags = FL_DST_AFTER;
+        }
+        // variants interleaved over three rounds, each timing two launches whose
+        // inputs and outputs rotate over the four temporaries (inputs are not
+        // left cache-resident by the previous launch); the best round counts
+        float tbest[RSFDE_PASS_VARIANTS];
+        for (int v = 0; v < RSFDE_PASS_VARIANTS; ++v) tbest[v] = 1e30f;
         const int L = I.ax[ax].L;
-        hipError_t e = launch_pass(L, fp == 1, t, ax > 0, h->stream);
-        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_pass(L, fp == 1, t, ax > 0, h->stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-          g_last_hip = e;
-          status = RSFDE_E_HIP;
-          break;
+        for (int rep = 0; rep < 3 && status == RSFDE_OK; ++rep) {
+          for (int v = 0; v < RSFDE_PASS_VARIANTS && status == RSFDE_OK; ++v) {
+            I.var[ax][fp][cls] = v;
+            PassArgs t = mk_pass(I, ax, op, fp == 1);
+            t.flags = flags;
+            hipError_t e = hipEventRecord(e0, h->stream);
+            for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+              const int k = 2 * rep + r + v;
+              t.in_c = I.tmp[k & 3];
+              t.in_a = I.tmp[(k + 1) & 3];
+              t.out_a = I.tmp[(k + 2) & 3];
+              t.out_c = I.tmp[(k + 3) & 3];
+              e = launch_pass(L, fp == 1, t, ax > 0, h->stream);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+              g_last_hip = e;
+              status = RSFDE_E_HIP;
+              break;
+            }
+            if (ms < tbest[v]) tbest[v] = ms;
+          }
         }
-        if (ms < best * 0.97f) {
-          best = ms;
-          bestv = v;
-        }
+        int bestv = 0;
+        for (int v = 1; v < RSFDE_PASS_VARIANTS; ++v)
+          if (tbest[v] < tbest[bestv] * 0.97f) bestv = v;
+        if (verbose)
+          fprintf(stderr, "rsfde autotune: axis %d %s %s pass: %.1f %.1f %.1f us per launch -> variant %d\n",
+                  ax, fp ? "fp32" : "fp64", cls ? "transform" : "operator", 500.f * tbest[0],
+                  500.f * tbest[1], 500.f * tbest[2], bestv);
+        I.var[ax][fp][cls] = bestv;
       }
-      I.var[ax][fp] = bestv;
     }
   }
   (void)hipEventDestroy(e0);

@@ -13,6 +13,8 @@
 // circulant embedding of the Toeplitz factors and the odd extension behind the
 // type-I sine transform (Section 3, eq. diag).
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 
 template <int L> struct FftPlan;
@@ -65,92 +67,67 @@ struct LdsSeq {
   __device__ __forceinline__ R& comp(int i, int c) const { return ((R*)(p + pos(i)))[c]; }
 };
 
-// Twiddles W_L^m = W_L^{m mod B} * W_L^{B floor(m/B)}: two short tables kept in
-// LDS (B + L/B entries) replace the length-L table in global memory.
-template <int L> struct TwSplit {
-  static constexpr int B = cgcd(L, 64);
-  static constexpr int NB = L / B;
-  static constexpr int size = B + NB;
-};
-
-// Fill the LDS twiddle tables from the global table tw[k] = exp(-2 pi i k / L).
-template <typename R, int L>
-__device__ __forceinline__ void twiddle_fill(cpx<R>* twl, const cpx<R>* __restrict__ tw, int tid,
-                                             int nt) {
-  using S = TwSplit<L>;
-  for (int i = tid; i < S::size; i += nt) twl[i] = i < S::B ? tw[i] : tw[(i - S::B) * S::B];
-}
-
-template <typename R, int L>
-__device__ __forceinline__ cpx<R> twiddle(const cpx<R>* twl, int m) {
-  using S = TwSplit<L>;
-  if constexpr (S::NB == 1) {
-    return twl[m];
-  } else {
-    return cmul(twl[m % S::B], twl[S::B + m / S::B]);
-  }
-}
-
 template <int L, int S> struct StageNs {
   static constexpr int value = StageNs<L, S - 1>::value * FftPlan<L>::R[S - 1];
 };
 template <int L> struct StageNs<L, 0> { static constexpr int value = 1; };
 
-template <int L, int S>
-struct TwOffset {  // first register slot of stage S
-  using P = FftPlan<L>;
-  static constexpr int value = TwOffset<L, S - 1>::value + (P::E / P::R[S - 1]) * (P::R[S - 1] - 1);
-};
-template <int L> struct TwOffset<L, 1> { static constexpr int value = 0; };
-template <int L> struct TwOffset<L, 0> { static constexpr int value = 0; };
-
-template <int L>
-struct TwTotal {
-  static constexpr int value = TwOffset<L, FftPlan<L>::NS>::value;
-};
-
-// Twiddles held in registers: each thread loads, once per kernel, exactly the
-// W_L^m its butterflies use (straight from the table, no products).
+// Twiddles W_L^m, m < L, from a half-length table in LDS: W_L^{m + L/2} = -W_L^m,
+// so entries m < L/2 suffice.  The table carries the same one-slot-per-256-byte
+// padding as the sequences, which spreads the strided twiddle reads of the last
+// stages over the banks.  Keeping twiddles in LDS instead of registers leaves
+// the registers to the butterflies and the batched global loads.
 template <typename R, int L>
-struct TwReg {
-  static constexpr int N = TwTotal<L>::value > 0 ? TwTotal<L>::value : 1;
-  cpx<R> w[N];
-  template <int S>
-  __device__ __forceinline__ void load_stage(const cpx<R>* __restrict__ g, int t) {
-    if constexpr (S < FftPlan<L>::NS) {
-      using P = FftPlan<L>;
-      constexpr int RAD = P::R[S], Ns = StageNs<L, S>::value, NB = P::E / RAD;
-      constexpr int step = L / (Ns * RAD), off = TwOffset<L, S>::value;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int k = (t + b * P::T) % Ns;
-#pragma unroll
-        for (int r = 1; r < RAD; ++r) w[off + b * (RAD - 1) + r - 1] = g[r * k * step];
-      }
-      load_stage<S + 1>(g, t);
-    }
-  }
-  __device__ __forceinline__ void load(const cpx<R>* __restrict__ g, int t) { load_stage<1>(g, t); }
-  template <int S>
-  __device__ __forceinline__ cpx<R> get(int b, int r, int /*m*/) const {
-    constexpr int RAD = FftPlan<L>::R[S];
-    return w[TwOffset<L, S>::value + b * (RAD - 1) + r - 1];
-  }
-};
-
-// Twiddles from the two-level LDS table (plans with many twiddles per thread).
-template <typename R, int L>
-struct TwLds {
+struct TwHalf {
+  static constexpr int H = L / 2;
+  static constexpr int BS = 256 / (int)sizeof(cpx<R>);
+  static constexpr int size = H + H / BS;
   const cpx<R>* tab;
+  __device__ __forceinline__ static constexpr int pos(int m) { return m + m / BS; }
   template <int S>
-  __device__ __forceinline__ cpx<R> get(int, int, int m) const { return twiddle<R, L>(tab, m); }
+  __device__ __forceinline__ cpx<R> get(int, int, int m) const {
+    const bool hi = m >= H;
+    const cpx<R> w = tab[pos(hi ? m - H : m)];
+    return hi ? -w : w;
+  }
 };
 
-// Registers when a thread needs at most 32 twiddles, else the LDS table.
-template <int L>
-struct TwUseReg {
-  static constexpr bool value = TwTotal<L>::value <= 32;
+// Compile-time loop: f(integral_constant<int, Q>) for Q = 0 .. C-1 (constant
+// indices keep small per-thread arrays in registers).
+template <int C, int Q = 0, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (Q < C) {
+    fn(std::integral_constant<int, Q>{});
+    static_for<C, Q + 1>(fn);
+  }
+}
+
+// This thread's share of the half table: loads (issued together) into v ...
+template <typename R, int L, int NT>
+struct TwFill {
+  static constexpr int H = TwHalf<R, L>::H;
+  static constexpr int C = (H + NT - 1) / NT;
 };
+// (real and imaginary parts in separate scalar arrays: they stay in registers)
+template <typename R, int L, int NT>
+__device__ __forceinline__ void tw_load(R* vr, R* vi, const cpx<R>* __restrict__ tw, int tid) {
+  constexpr int H = TwHalf<R, L>::H;
+  static_for<TwFill<R, L, NT>::C>([&](auto q) {
+    const int m = tid + q.value * NT;
+    const cpx<R> w = tw[m < H ? m : 0];
+    vr[q.value] = w.x;
+    vi[q.value] = w.y;
+  });
+}
+// ... then stores into the LDS table (a barrier must follow before use)
+template <typename R, int L, int NT>
+__device__ __forceinline__ void tw_store(const R* vr, const R* vi, cpx<R>* tab, int tid) {
+  constexpr int H = TwHalf<R, L>::H;
+  static_for<TwFill<R, L, NT>::C>([&](auto q) {
+    const int m = tid + q.value * NT;
+    if (H % NT == 0 || m < H) tab[TwHalf<R, L>::pos(m)] = cpx<R>{vr[q.value], vi[q.value]};
+  });
+}
 
 // ---- small DFTs; DIR = -1 forward (e^{-2 pi i nk/R}), +1 backward ----------
 

@@ -53,7 +53,6 @@ struct GmresState {
   double Rm[RSFDE_MAX_RESTART * RSFDE_MAX_RESTART];  // R(i,j) at [j*MAX + i]
   double vsc[RSFDE_MAX_RESTART + 1];
   double h[RSFDE_MAX_RESTART + 1], h2[RSFDE_MAX_RESTART + 1];
-  double y[RSFDE_MAX_RESTART];
 };
 
 // Partial sums are stored value-major: partial[k * RSFDE_PVS + block].
@@ -85,108 +84,159 @@ struct GmOut {
   double sc;         // scale of column j (vsc[j])
 };
 
-// Deterministic block sum of one value per thread (any multiple-of-64 block).
-__device__ __forceinline__ double gm_block_sum(double x, double* sh /* >= 16 */) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) sh[wv] = x;
-  __syncthreads();
-  double s = 0.0;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int w = 0; w < nw; ++w) s += sh[w];
-  __syncthreads();
-  return s;
+// Resolve outputs kept in LDS for the kernel that ran the prologue: the rotated
+// Hessenberg column of the resolved step (R(0..j, j)) and its rotated
+// right-hand-side entry, for a back substitution in the same kernel.
+struct GmCol {
+  double rc[RSFDE_MAX_RESTART + 1];
+  double gj;
+  int j;  // resolved step, or -1
+};
+
+// Lane i's value of x, broadcast to the whole wavefront (i uniform).
+__device__ __forceinline__ double gm_lane(double x, int i) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, i);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Prologue shared by the first operator pass and the update kernel.  All
-// threads of the block must call it.  On return `o` (shared) holds the status
-// and, when this kernel resolved a finishing step and want_y, y[0..k) is in ysh.
-__device__ __forceinline__ void gm_prologue(const GmRes& g, GmOut* o, double* ysh, bool want_y) {
-  __shared__ double sh[16];
-  __shared__ double hc[RSFDE_MAX_RESTART + 1];  // Hessenberg column (LDS, not private memory)
+// Everything the resolve reads from the state, fetched by the first wavefront
+// (lane i: Hessenberg entries h_i, h2_i and rotation i) in one round of
+// unconditional loads at clamped indices: no branch and no use of a loaded value
+// sits between the loads, so none of them waits for another (or for the tile
+// loads issued after them).
+struct GmIn {
+  double pv[RSFDE_PVS / 64];  // sweep-3 partials lane + 64 q
+  double h, h2, cs, sn;
+  double gam, thr, vsc;
+  int fl, kfin;
+};
+
+__device__ __forceinline__ void gm_fetch(const GmRes& g, GmIn& in) {
+  const GmresState* st = g.st;
+  const int lane = threadIdx.x;
+  const int j = g.pend;  // -1: nothing to resolve
+  const int jj = j < 0 ? 0 : j;
+  in.fl = st->FL[j >= 0 ? j : g.j];
+  in.kfin = st->kfin;
+  in.vsc = st->vsc[g.j];
+  const double* p3 = j >= 0 ? g.p3 : st->h;
+#pragma unroll
+  for (int q = 0; q < RSFDE_PVS / 64; ++q) {
+    const int b = lane + 64 * q;
+    in.pv[q] = p3[j >= 0 && b < g.nb3 ? b : 0];
+  }
+  const int lh = lane <= jj ? lane : 0, lr = lane < jj ? lane : 0;
+  in.h = st->h[lh];
+  in.h2 = st->h2[lh];
+  in.cs = st->cs[lr];
+  in.sn = st->sn[lr];
+  in.gam = st->gam[jj];
+  in.thr = st->sum.thr;
+}
+
+// Resolve of step `pend` from the fetched values (first wavefront), then one
+// barrier.  The earlier rotations are applied in order with values broadcast
+// from their lanes, followed by the new Givens rotation and the stopping test
+// (Lemma Krylov: |g_{j+1}| is the residual norm of the least-squares problem).
+// On return `o` (shared) holds the status and `col` the resolved column.
+__device__ __forceinline__ void gm_resolve(const GmRes& g, const GmIn& in, GmOut* o, GmCol* col) {
   GmresState* st = g.st;
-  const bool cand = g.pend >= 0;
-  const int fl_prev = st->FL[cand ? g.pend : g.j];
-  double part = 0.0;
-  if (cand && fl_prev == GM_RUNNING)
-    for (int b = threadIdx.x; b < g.nb3; b += blockDim.x) part += g.p3[b];
-  const double nu = gm_block_sum(part, sh);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const bool cand = g.pend >= 0;
+    const int j = g.pend;
+    const int fl_prev = in.fl;
     if (!cand) {
-      o->flag = fl_prev == GM_UNSET ? GM_CONVERGED : fl_prev;
-      o->sc = st->vsc[g.j];
-      o->k = st->kfin;
-      if (fl_prev != GM_RUNNING && fl_prev != GM_NONFINITE && want_y)
-        for (int i = 0; i < o->k; ++i) ysh[i] = st->y[i];
-    } else if (fl_prev != GM_RUNNING) {
-      // the cycle ended before step `pend`: its resolve stored kfin and y
-      o->flag = fl_prev == GM_UNSET ? GM_CONVERGED : fl_prev;
-      o->k = st->kfin;
-      o->sc = 0.0;
-      if (fl_prev != GM_NONFINITE && want_y)
-        for (int i = 0; i < o->k; ++i) ysh[i] = st->y[i];
-    } else {
-      // resolve step j = pend: Hessenberg column, Givens rotation, stopping test
-      const int j = g.pend;
-      const int MX = RSFDE_MAX_RESTART;
-      const bool writer = blockIdx.x == 0;
-      for (int i = 0; i <= j; ++i) hc[i] = st->h[i] + st->h2[i];
-      const double hn = sqrt(nu);
-      double hsz = 0.0;
-      for (int i = 0; i <= j; ++i) hsz = fmax(hsz, fabs(hc[i]));
-      const bool breakdown = !(hn > 1e-14 * hsz);
-      for (int i = 0; i < j; ++i) {
-        const double p = hc[i], q = hc[i + 1];
-        hc[i] = st->cs[i] * p + st->sn[i] * q;
-        hc[i + 1] = -st->sn[i] * p + st->cs[i] * q;
+      if (lane == 0) {
+        o->flag = fl_prev == GM_UNSET ? GM_CONVERGED : fl_prev;
+        o->sc = in.vsc;
+        o->k = in.kfin;
+        col->j = -1;
       }
-      const double r = hypot(hc[j], hn);
-      const double c = r > 0.0 ? hc[j] / r : 1.0;
-      const double s = r > 0.0 ? hn / r : 0.0;
-      const double gj = c * st->gam[j];
-      const double gn = -s * st->gam[j];
+    } else if (fl_prev != GM_RUNNING) {
+      // the cycle ended before step `pend`: its resolve stored kfin
+      if (lane == 0) {
+        o->flag = fl_prev == GM_UNSET ? GM_CONVERGED : fl_prev;
+        o->k = in.kfin;
+        o->sc = 0.0;
+        col->j = -1;
+      }
+    } else {
+      const double hl = lane <= j ? in.h + in.h2 : 0.0;
+      const double cl = lane < j ? in.cs : 0.0;
+      const double sl = lane < j ? in.sn : 0.0;
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < RSFDE_PVS / 64; ++q) part += lane + 64 * q < g.nb3 ? in.pv[q] : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+      double hsz = fabs(hl);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) hsz = fmax(hsz, __shfl_xor(hsz, off, 64));
+      const double nu = gm_lane(part, 0);  // one lane's sum: the same bits in every block
+      const double hn = sqrt(nu);
+      const bool breakdown = !(hn > 1e-14 * hsz);
+      double p = gm_lane(hl, 0);
+      double rcl = 0.0;  // lane i keeps R(i, j)
+      for (int i = 0; i < j; ++i) {
+        const double c = gm_lane(cl, i), sg = gm_lane(sl, i), q = gm_lane(hl, i + 1);
+        const double ri = c * p + sg * q;
+        p = -sg * p + c * q;
+        if (lane == i) rcl = ri;
+      }
+      const double r = hypot(p, hn);
+      const double c = r > 0.0 ? p / r : 1.0;
+      const double sg = r > 0.0 ? hn / r : 0.0;
+      const double gj = c * in.gam;
+      const double gn = -sg * in.gam;
       const double rr = fabs(gn);
       const double vn = hn > 0.0 ? 1.0 / hn : 0.0;
+      if (lane == j) rcl = r;
       int flag;
       if (!isfinite(rr) || !isfinite(r)) flag = GM_NONFINITE;
-      else if (rr <= st->sum.thr) flag = GM_CONVERGED;
+      else if (rr <= in.thr) flag = GM_CONVERGED;
       else if (breakdown) flag = GM_BREAKDOWN;
       else if (j + 1 >= g.m) flag = GM_CYCLE_FULL;
       else flag = GM_RUNNING;
-      const int k = j + 1;
       const bool fin = flag != GM_RUNNING && flag != GM_NONFINITE;
-      if (fin && (want_y || writer)) {
-        // back substitution R y = g (column j of R is hc[0..j-1], r)
-        for (int i = k - 1; i >= 0; --i) {
-          double sacc = i == j ? gj : st->gfin[i];
-          for (int l = i + 1; l < k; ++l) sacc -= (l == j ? hc[i] : st->Rm[l * MX + i]) * ysh[l];
-          ysh[i] = sacc / (i == j ? r : st->Rm[i * MX + i]);
+      if (lane <= j) col->rc[lane] = rcl;
+      if (blockIdx.x == 0) {
+        constexpr int MX = RSFDE_MAX_RESTART;
+        if (lane <= j) st->Rm[j * MX + lane] = rcl;
+        if (lane == 0) {
+          st->cs[j] = c;
+          st->sn[j] = sg;
+          st->gfin[j] = gj;
+          st->gam[j + 1] = gn;
+          st->vsc[j + 1] = vn;
+          st->FL[j + 1] = flag;
+          st->sum.res = rr;
+          st->sum.flag = flag;
+          if (fin) {
+            st->kfin = j + 1;
+            st->sum.k = j + 1;
+          }
         }
       }
-      if (writer) {
-        st->cs[j] = c;
-        st->sn[j] = s;
-        for (int i = 0; i < j; ++i) st->Rm[j * MX + i] = hc[i];
-        st->Rm[j * MX + j] = r;
-        st->gfin[j] = gj;
-        st->gam[j + 1] = gn;
-        st->vsc[j + 1] = vn;
-        st->FL[j + 1] = flag;
-        st->sum.res = rr;
-        st->sum.flag = flag;
-        if (fin) {
-          st->kfin = k;
-          st->sum.k = k;
-          for (int i = 0; i < k; ++i) st->y[i] = ysh[i];
-        }
+      if (lane == 0) {
+        col->gj = gj;
+        col->j = j;
+        o->flag = flag;
+        o->k = fin ? j + 1 : 0;
+        o->sc = vn;
       }
-      o->flag = flag;
-      o->k = fin ? k : 0;
-      o->sc = vn;
     }
   }
   __syncthreads();
+}
+
+// Fetch and resolve (for kernels with nothing to overlap the fetch with).
+__device__ __forceinline__ void gm_prologue(const GmRes& g, GmOut* o, GmCol* col) {
+  GmIn in;
+  if (threadIdx.x < 64) gm_fetch(g, in);
+  gm_resolve(g, in, o, col);
 }
 
 struct KryArgs {

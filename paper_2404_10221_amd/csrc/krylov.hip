@@ -240,13 +240,35 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep3(const KryArgs a) 
 __global__ void __launch_bounds__(256)
 k_update(const double* __restrict__ V, int64_t ldv, int64_t n, double* __restrict__ x,
          const GmRes g) {
+  constexpr int MX = RSFDE_MAX_RESTART;
   __shared__ GmOut o;
-  __shared__ double ysh[RSFDE_MAX_RESTART];
-  __shared__ double cf[RSFDE_MAX_RESTART];
-  gm_prologue(g, &o, ysh, true);
+  __shared__ GmCol col;
+  __shared__ double Rs[MX * MX];  // R(i, l) at [l * MX + i], columns l < k
+  __shared__ double gs[MX];
+  __shared__ double cf[MX];
+  gm_prologue(g, &o, &col);
   const int flag = o.flag, k = o.k;
   if (flag == GM_RUNNING || flag == GM_NONFINITE || k <= 0) return;
-  if ((int)threadIdx.x < k) cf[threadIdx.x] = ysh[threadIdx.x] * g.st->vsc[threadIdx.x];
+  // stage the triangular factor and the rotated right-hand side: column k-1 comes
+  // from this kernel's resolve when it ran here, the others from the state
+  const GmresState* st = g.st;
+  const int jr = col.j;
+  for (int idx = threadIdx.x; idx < k * MX; idx += blockDim.x) {
+    const int l = idx / MX, i = idx - l * MX;
+    if (i <= l) Rs[idx] = l == jr ? col.rc[i] : st->Rm[idx];
+  }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = i == jr ? col.gj : st->gfin[i];
+  __syncthreads();
+  // back substitution R y = g by columns, one wavefront: lane i holds g_i
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    double gl = lane < k ? gs[lane] : 0.0;
+    for (int i = k - 1; i >= 0; --i) {
+      const double yi = __shfl(gl, i, 64) / Rs[i * MX + i];
+      if (lane < i) gl -= Rs[i * MX + lane] * yi;
+      if (lane == i) cf[i] = yi * st->vsc[i];
+    }
+  }
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t n2 = n >> 1, ld2 = ldv >> 1;

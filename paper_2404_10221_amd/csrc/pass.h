@@ -97,10 +97,10 @@ template <typename R, int L, bool STRIDED, int VAR>
 struct PassShape {
   static constexpr int T = FftPlan<L>::T;
   static constexpr int bytes_per_fft = (LdsSeq<R, L>::size + 4) * (int)sizeof(cpx<R>);
-  // LDS left for the transforms: 160 KB minus twiddles, the circulant spectrum
+  // LDS left for the transforms: 160 KB minus the twiddle table, the circulant spectrum
   // and 2 KB for the small shared arrays (block sums, Givens column, y)
   static constexpr int cap =
-      160 * 1024 - TwSplit<L>::size * (int)sizeof(cpx<R>) - L * (int)sizeof(R) - 2048;
+      160 * 1024 - TwHalf<R, L>::size * (int)sizeof(cpx<R>) - L * (int)sizeof(R) - 2048;
   static constexpr int want = 512 / T > 1 ? 512 / T : 1;
   static constexpr int lim = cap / bytes_per_fft;
   static constexpr int F0a = want < lim ? want : lim;
@@ -121,18 +121,11 @@ rsfde_pass_kernel(const PassArgs a) {
   constexpr int LP = LdsSeq<R, L>::size + 4;
   constexpr int NE = STRIDED ? E : E / 2;  // element slots per thread
   __shared__ cpx<R> lds[F * LP];
-  __shared__ cpx<R> twl[TwUseReg<L>::value ? 1 : TwSplit<L>::size];
+  __shared__ cpx<R> twl[TwHalf<R, L>::size];
   __shared__ R chs[L];  // circulant spectrum / L (operator passes)
 
   const int tid = threadIdx.x;
-  using TWP = typename std::conditional<TwUseReg<L>::value, TwReg<R, L>, TwLds<R, L>>::type;
-  TWP tw;
-  if constexpr (TwUseReg<L>::value) {
-    tw.load((const cpx<R>*)a.tw, tid % FftPlan<L>::T);
-  } else {
-    twiddle_fill<R, L>(twl, (const cpx<R>*)a.tw, tid, NT);
-    tw.tab = twl;
-  }
+  const TwHalf<R, L> tw{twl};
   const int f = tid / T;
   const int t = tid - f * T;
   const LdsSeq<R, L> buf{lds + f * LP};
@@ -172,11 +165,97 @@ rsfde_pass_kernel(const PassArgs a) {
   };
   auto c_row = [&](int comp) -> int64_t { return row0 + 2 * f + comp; };
 
+  // ---- the first wavefront fetches the state of the pending Givens resolve
+  // before the tile's loads are issued, so the resolve can start while they fly
+  GmIn gin;
+  if (a.use_gm && tid < 64) gm_fetch(a.gm, gin);
+
+  // ---- issue every global load of the tile first, at clamped addresses and
+  // with no branch around them: one memory latency then covers the whole load
+  // phase, and it overlaps the prologue below (slots past the pencil end or the
+  // tile's last pencil are loaded from a valid address and discarded).
+  constexpr int NL = STRIDED ? NE : 2 * NE;  // values per input array per thread
+  R lc[NL], la[NL];
+  {
+    const bool ld_a = a.op <= OP_MV_LAST;
+    if constexpr (!STRIDED) {
+      const int64_t r0 = 2 * f < nvalid ? c_row(0) : 0;
+      const int64_t r1 = 2 * f + 1 < nvalid ? c_row(1) : 0;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = t + i * T;
+        const int pc = p < N ? p : 0;
+        lc[2 * i] = ld_any<R>(a.in_c, r0 * N + pc, in64);
+        lc[2 * i + 1] = ld_any<R>(a.in_c, r1 * N + pc, in64);
+        if (ld_a) {
+          la[2 * i] = ld_any<R>(a.in_a, r0 * N + pc, false);
+          la[2 * i + 1] = ld_any<R>(a.in_a, r1 * N + pc, false);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        int p, pp;
+        s_pos(i, p, pp);
+        const int64_t g = gbase + (int64_t)(p < N ? p : 0) * inner + (pp < nvalid ? pp : 0);
+        lc[i] = ld_any<R>(a.in_c, g, in64);
+        if (ld_a) la[i] = ld_any<R>(a.in_a, g, false);
+      }
+    }
+  }
+  // Tables for LDS (chs) join the batch: the circulant spectrum of the operator
+  // passes, or the axis-0 eigenvalue tables lambda (first N entries) and
+  // eta q / lambda (next N) of the transform-scale-transform pass, plus that
+  // pass's per-pencil factors from the other (already transformed) axes.
+  constexpr int CH = (L + NT - 1) / NT;
+  const bool is_dsd = a.op == OP_DSD;
+  R lt[CH];
+  R twr[TwFill<R, L, NT>::C], twi[TwFill<R, L, NT>::C];
+  tw_load<R, L, NT>(twr, twi, (const cpx<R>*)a.tw, tid);
+  R rl[2][2], rw[2][2];  // [pencil of the pair][axis 1, 2]: lambda and eta q / lambda
+  R ebv = (R)0;
+  if (a.op <= OP_MV_LAST) {
+    const R* __restrict__ cg = (const R*)a.chat;
+    static_for<CH>([&](auto q) {
+      const int k = tid + q.value * NT;
+      lt[q.value] = cg[k < L ? k : 0];
+    });
+  } else if (is_dsd) {
+    const R* __restrict__ l0 = (const R*)a.lam[0];
+    const R* __restrict__ w0 = (const R*)a.wq[0];
+    static_for<CH>([&](auto q) {
+      const int k = tid + q.value * NT;
+      const R lv = l0[k < N ? k : 0];  // both loads in bounds
+      const R wv = w0[k >= N && k < 2 * N ? k - N : 0];
+      lt[q.value] = k < N ? lv : wv;
+    });
+    if constexpr (!STRIDED) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        int64_t rr = c_row(c);
+        if (rr >= a.npencil) rr = 0;
+#pragma unroll
+        for (int l = 1; l < 3; ++l) {
+          if (l < a.d) {
+            const int64_t k = rr % a.Nax[l];
+            rr /= a.Nax[l];
+            rl[c][l - 1] = ((const R*)a.lam[l])[k];
+            rw[c][l - 1] = ((const R*)a.wq[l])[k];
+          } else {
+            rl[c][l - 1] = (R)1;
+            rw[c][l - 1] = (R)0;
+          }
+        }
+      }
+    }
+    ebv = (R)(*a.ebar);
+  }
+
   R sc = (R)1;
   if (a.use_gm) {
     __shared__ GmOut go;
-    __shared__ double gy[RSFDE_MAX_RESTART];
-    gm_prologue(a.gm, &go, gy, false);
+    __shared__ GmCol gcol;
+    gm_resolve(a.gm, gin, &go, &gcol);
     if (go.flag != GM_RUNNING) return;  // same value in every thread
     sc = (R)go.sc;
   } else {
@@ -185,9 +264,12 @@ rsfde_pass_kernel(const PassArgs a) {
   }
   const R bd = (R)a.bd, bo = (R)a.bo, eta = (R)a.eta;
   const R* __restrict__ chat = chs;
-  if (a.op <= OP_MV_LAST) {
-    const R* __restrict__ cg = (const R*)a.chat;
-    for (int k = tid; k < L; k += NT) chs[k] = cg[k];
+  tw_store<R, L, NT>(twr, twi, twl, tid);
+  if (a.op <= OP_MV_LAST || is_dsd) {
+    static_for<CH>([&](auto q) {
+      const int k = tid + q.value * NT;
+      if (L % NT == 0 || k < L) chs[k] = lt[q.value];
+    });
   }
 
   cpx<R> ra[STRIDED ? 1 : NE];  // contiguous: packed pair per slot
@@ -209,15 +291,14 @@ rsfde_pass_kernel(const PassArgs a) {
     }
     if constexpr (!STRIDED) {
       const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
-      const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         const int p = t + i * T;
         if (p < N) {
-          R c0 = v0 ? ld_any<R>(a.in_c, b0 + p, in64) * sc : (R)0;
-          R c1 = v1 ? ld_any<R>(a.in_c, b1 + p, in64) * sc : (R)0;
-          R a0 = v0 ? ld_any<R>(a.in_a, b0 + p, false) : (R)0;
-          R a1 = v1 ? ld_any<R>(a.in_a, b1 + p, false) : (R)0;
+          R c0 = v0 ? lc[2 * i] * sc : (R)0;
+          R c1 = v1 ? lc[2 * i + 1] * sc : (R)0;
+          R a0 = v0 ? la[2 * i] : (R)0;
+          R a1 = v1 ? la[2 * i + 1] : (R)0;
           if (ev_mode) {
             a0 *= c0;
             a1 *= c1;
@@ -233,9 +314,8 @@ rsfde_pass_kernel(const PassArgs a) {
         s_pos(i, p, pp);
         if (p < N) {
           const bool v = pp < nvalid;
-          const int64_t g = gbase + (int64_t)p * inner + pp;
-          R c = v ? ld_any<R>(a.in_c, g, in64) * sc : (R)0;
-          R av = v ? ld_any<R>(a.in_a, g, false) : (R)0;
+          R c = v ? lc[i] * sc : (R)0;
+          R av = v ? la[i] : (R)0;
           if (ev_mode) av *= c;
           LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           set_comp(bb[p], pp & 1, c);
@@ -292,6 +372,28 @@ rsfde_pass_kernel(const PassArgs a) {
     const bool want_dst = last && (a.flags & (FL_DST_AFTER | FL_PREC_FULL));
     const R gam = (R)a.gam, xcoef = (R)a.xcoef;
     const double* __restrict__ xin = a.in_x;
+    // additive vector (right-hand side chains only): all loads issued together
+    R lx[NL];
+    if (last && xin) {
+      if constexpr (!STRIDED) {
+        const int64_t r0 = 2 * f < nvalid ? c_row(0) : 0;
+        const int64_t r1 = 2 * f + 1 < nvalid ? c_row(1) : 0;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+          const int p = t + i * T;
+          const int pc = p < N ? p : 0;
+          lx[2 * i] = (R)xin[r0 * N + pc];
+          lx[2 * i + 1] = (R)xin[r1 * N + pc];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+          int p, pp;
+          s_pos(i, p, pp);
+          lx[i] = (R)xin[gbase + (int64_t)(p < N ? p : 0) * inner + (pp < nvalid ? pp : 0)];
+        }
+      }
+    }
     if constexpr (!STRIDED) {
       const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
       const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
@@ -303,8 +405,8 @@ rsfde_pass_kernel(const PassArgs a) {
           if (last) {
             w = w * gam;
             if (xin) {
-              R x0 = v0 ? (R)xin[b0 + p] : (R)0;
-              R x1 = v1 ? (R)xin[b1 + p] : (R)0;
+              R x0 = v0 ? lx[2 * i] : (R)0;
+              R x1 = v1 ? lx[2 * i + 1] : (R)0;
               w = w + cpx<R>{x0, x1} * xcoef;
             }
           }
@@ -329,7 +431,7 @@ rsfde_pass_kernel(const PassArgs a) {
           R w = rs[i] + comp_of(bb[p], c) * eta;
           if (last) {
             w = w * gam;
-            if (xin && v) w += (R)xin[g] * xcoef;
+            if (xin && v) w += lx[i] * xcoef;
           }
           if (want_dst) {
             rs[i] = w;
@@ -378,13 +480,12 @@ rsfde_pass_kernel(const PassArgs a) {
     }
     if constexpr (!STRIDED) {
       const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
-      const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         const int p = t + i * T;
         if (p < N) {
-          R x0 = v0 ? ld_any<R>(a.in_c, b0 + p, in64) : (R)0;
-          R x1 = v1 ? ld_any<R>(a.in_c, b1 + p, in64) : (R)0;
+          R x0 = v0 ? lc[2 * i] : (R)0;
+          R x1 = v1 ? lc[2 * i + 1] : (R)0;
           cpx<R> z{x0, x1};
           buf[p + 1] = z;
           buf[L - 1 - p] = -z;
@@ -397,7 +498,7 @@ rsfde_pass_kernel(const PassArgs a) {
         s_pos(i, p, pp);
         if (p < N) {
           const bool v = pp < nvalid;
-          R x = v ? ld_any<R>(a.in_c, gbase + (int64_t)p * inner + pp, in64) : (R)0;
+          R x = v ? lc[i] : (R)0;
           LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           set_comp(bb[p + 1], pp & 1, x);
           set_comp(bb[L - 1 - p], pp & 1, -x);
@@ -414,21 +515,39 @@ rsfde_pass_kernel(const PassArgs a) {
   if (scale_phase) {
     // 1/mu_K in the sine basis (eq. Pa, Lemma le:eig, Lemma Heig, eq. q); the
     // pass runs along axis 0, the other axes are already transformed.
-    const R* lam0 = (const R*)a.lam[0];
-    const R* wq0 = (const R*)a.wq[0];
-    const R eb = (R)(*a.ebar);
     const R ps = (R)a.pscale;
-    R Lam[2] = {(R)1, (R)1}, Sig[2] = {(R)0, (R)0};
     if constexpr (!STRIDED) {
+      R eb, Lam[2], Sig[2], l0v[NE], w0v[NE];
+      if (is_dsd) {
+        // lambda and eta q / lambda of axis 0 are in chs[0, N) and chs[N, 2N)
+        eb = ebv;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        int64_t rr = c_row(c);
-        if (rr >= a.npencil) rr = 0;
-        for (int l = 1; l < a.d; ++l) {
-          const int64_t k = rr % a.Nax[l];
-          rr /= a.Nax[l];
-          Lam[c] *= ((const R*)a.lam[l])[k];
-          Sig[c] += ((const R*)a.wq[l])[k];
+        for (int c = 0; c < 2; ++c) {
+          Lam[c] = ((R)1 * rl[c][0]) * rl[c][1];
+          Sig[c] = ((R)0 + rw[c][0]) + rw[c][1];
+        }
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+          const int pc = t + i * T < N ? t + i * T : 0;
+          l0v[i] = chs[pc];
+          w0v[i] = chs[N + pc];
+        }
+      } else {
+        // one-axis operator pass followed by the preconditioner: chs holds the
+        // circulant spectrum, the tables come from global memory (one batch)
+        eb = (R)(*a.ebar);
+        const R* __restrict__ lam0 = (const R*)a.lam[0];
+        const R* __restrict__ wq0 = (const R*)a.wq[0];
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+          const int pc = t + i * T < N ? t + i * T : 0;
+          l0v[i] = lam0[pc];
+          w0v[i] = wq0[pc];
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          Lam[c] = (R)1;
+          Sig[c] = (R)0;
         }
       }
 #pragma unroll
@@ -436,7 +555,7 @@ rsfde_pass_kernel(const PassArgs a) {
         const int p = t + i * T;
         if (p < N) {
           const cpx<R> Z = buf[p + 1];
-          const R l0 = lam0[p], w0 = wq0[p];
+          const R l0 = l0v[i], w0 = w0v[i];
           const R s0 = ps / (Lam[0] * l0 * (eb + w0 + Sig[0]));
           const R s1 = ps / (Lam[1] * l0 * (eb + w0 + Sig[1]));
           ra[i] = cpx<R>{-Z.y * s0, Z.x * s1};

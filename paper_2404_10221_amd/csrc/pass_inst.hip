@@ -22,11 +22,12 @@ k_spectrum(const double* __restrict__ s, int N, const cpx<double>* __restrict__ 
   constexpr int T = FftPlan<L>::T;
   __shared__ cpx<double> bufs[LdsSeq<double, L>::size];
   const LdsSeq<double, L> buf{bufs};
-  __shared__ cpx<double> twl[TwSplit<L>::size];
+  __shared__ cpx<double> twl[TwHalf<double, L>::size];
   const int t = threadIdx.x;
-  twiddle_fill<double, L>(twl, tw, t, T);
-  TwLds<double, L> twp;
-  twp.tab = twl;
+  double twr[TwFill<double, L, T>::C], twi[TwFill<double, L, T>::C];
+  tw_load<double, L, T>(twr, twi, tw, t);
+  tw_store<double, L, T>(twr, twi, twl, t);
+  const TwHalf<double, L> twp{twl};
   for (int k = t; k < L; k += T) {
     double c = 0.0;
     if (k < N) c = s[k];
