@@ -47,6 +47,9 @@ WORKLOAD_TEXT = {
           "u=e^-t prod x_i^2(1-x_i)^2, dt=1/16, GMRES(30) rtol 1e-10, FP64",
     "C5": "C5: 3-D N=511^3, alpha=(1.4,1.6,1.9), kappa=(1,0.8,0.6), e=2+prod sin(pi x_i) cos t, "
           "f=8x8x8 seeded sine modes, psi=0, dt=1/8, GMRES(20) rtol 1e-10, FP64",
+    "C4": "C4: 64 independent 2-D instances, N_i in {127,255,383,511} per axis (6.5M unknowns), "
+          "alpha_i~U(1.1,1.9), kappa_i~U(0.2,2), e=1+U*g, f=8x8 seeded sine modes, psi=0, dt=1/16, "
+          "GMRES(30) rtol 1e-10, FP64, batched launches; a step advances all 64",
 }
 
 
@@ -76,42 +79,83 @@ def read_traffic(workload: str, kclass: str):
 
 
 class Stepper:
-    """Owns a handle on one instance and steps it with device-evaluated fields."""
+    """Owns a handle on one or more instances (several: batched launches) and steps
+    them together with device-evaluated fields."""
 
-    def __init__(self, inst, **over):
+    def __init__(self, insts, **over):
         import torch
         from paper_2404_10221_amd import rsfde as R
         self.R = R
-        self.inst = inst
-        self.S = R.Solver([R.params_from_instance(inst, **over)])
-        R.rsfde_set_fields(self.S.h, 0, inst.e, inst.f, inst.psi)
-        R.rsfde_prescan_ebar(self.S.h, 0, inst.M)
-        self.u = torch.empty(inst.size, dtype=torch.float64, device="cuda")
-        self.e = torch.empty(inst.size, dtype=torch.float64, device="cuda")
-        ncl = 1
-        for v in inst.n:
-            ncl *= v + 2
-        self.f = torch.empty(ncl, dtype=torch.float64, device="cuda")
-        R.rsfde_eval_field(self.S.h, 0, R.WHICH_PSI, 0.0, self.u)
-        self.f_time_dep = inst.f.time_dependent
-        R.rsfde_eval_field(self.S.h, 0, R.WHICH_F, 0.5 * inst.dt, self.f)
+        self.insts = list(insts) if isinstance(insts, (list, tuple)) else [insts]
+        self.inst = self.insts[0]
+        self.S = R.Solver([R.params_from_instance(i, **over) for i in self.insts])
+        self.us, self.es, self.fs = [], [], []
+        for k, inst in enumerate(self.insts):
+            R.rsfde_set_fields(self.S.h, k, inst.e, inst.f, inst.psi)
+            R.rsfde_prescan_ebar(self.S.h, k, inst.M)
+            ncl = 1
+            for v in inst.n:
+                ncl *= v + 2
+            self.us.append(torch.empty(inst.size, dtype=torch.float64, device="cuda"))
+            self.es.append(torch.empty(inst.size, dtype=torch.float64, device="cuda"))
+            self.fs.append(torch.empty(ncl, dtype=torch.float64, device="cuda"))
+            R.rsfde_eval_field(self.S.h, k, R.WHICH_PSI, 0.0, self.us[k])
+            R.rsfde_eval_field(self.S.h, k, R.WHICH_F, 0.5 * inst.dt, self.fs[k])
+        self.u = self.us[0]
         self.m = 0
         self.iters = 0
         self.status = 0
 
     def step(self):
         R = self.R
-        th = (self.m + 0.5) * self.inst.dt
-        R.rsfde_eval_field(self.S.h, 0, R.WHICH_E, th, self.e)
-        if self.f_time_dep:
-            R.rsfde_eval_field(self.S.h, 0, R.WHICH_F, th, self.f)
-        s, st = R.rsfde_step(self.S.h, self.m * self.inst.dt, [self.e], [self.f], [self.u])
+        for k, inst in enumerate(self.insts):
+            th = (self.m + 0.5) * inst.dt
+            R.rsfde_eval_field(self.S.h, k, R.WHICH_E, th, self.es[k])
+            if inst.f.time_dependent:
+                R.rsfde_eval_field(self.S.h, k, R.WHICH_F, th, self.fs[k])
+        s, st = R.rsfde_step(self.S.h, self.m * self.inst.dt, self.es, self.fs, self.us)
         self.status = max(self.status, s)
-        self.iters += st[0]["iters"]
+        self.iters += sum(x["iters"] for x in st)
         self.m += 1
 
     def close(self):
         self.S.close()
+
+
+def cpu_baseline_batch(insts, nsample: int):
+    """Many-instance workload: time the FP64 oracle on one step of the first
+    `nsample` instances and scale to the whole batch by unknown count; parity of
+    the batched GPU step on the same instances."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    sample = insts[:nsample]
+    t0 = time.perf_counter()
+    refs = []
+    for inst in sample:
+        P = O.OracleProblem(inst)
+        u, _ = P.step(P.psi(), 0)
+        refs.append(u.ravel())
+    dt = time.perf_counter() - t0
+    n_s = sum(i.size for i in sample)
+    n_all = sum(i.size for i in insts)
+    g = Stepper(insts)
+    g.step()
+    par = 0.0
+    for k, ref in enumerate(refs):
+        got = g.us[k].cpu().numpy()
+        par = max(par, float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)))
+    g.close()
+    return {
+        "value": (n_s / n_all) / dt, "unit": "time-steps/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"first step of instances 0..{nsample - 1} ({n_s} of {n_all} unknowns) in {dt:.1f} s, "
+                  f"scaled to the whole batch by unknown count",
+        "parity_rel_diff_gpu_vs_oracle": par,
+    }
 
 
 def cpu_baseline(inst, steps: int):
@@ -155,7 +199,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--workload", default="C2", choices=("C1", "C2", "C3", "C5"))
+    ap.add_argument("--cpu-instances", type=int, default=4,
+                    help="instances of a many-instance workload the oracle baseline samples")
+    ap.add_argument("--workload", default="C2", choices=("C1", "C2", "C3", "C4", "C5"))
     ap.add_argument("--timing-every", type=int, default=4,
                     help="time one launch in this many of the dominant kernel class")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -181,11 +227,14 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8,
                           "launches": 3}), flush=True)
         return
-    inst = config(args.workload)
+    cfg = config(args.workload)
+    insts = cfg if isinstance(cfg, list) else [cfg]
+    inst = insts[0]
+    unknowns = sum(i.size for i in insts)
     K, W = args.steps, args.warmup
 
     # ---- FP64 form: warm-up with every kernel class timed (to find the dominant one)
-    g = Stepper(inst)
+    g = Stepper(insts)
     R.rsfde_set_timing(g.S.h, (1 << len(KCLASS_NAMES)) - 1, 1)
     for _ in range(W):
         g.step()
@@ -208,7 +257,7 @@ def main():
     R.rsfde_set_timing(g.S.h, 0, 1)
     elapsed = t1 - t0
     iters = g.iters - it0
-    u64 = g.u.clone()
+    u64 = [u.clone() for u in g.us]
     status = g.status
     g.close()
     achieved = (by / n) / ((ms / n) * 1e-3) / 1e9 if n else 0.0
@@ -227,7 +276,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
-                   "unknowns": inst.size, "gmres_iters_per_step": iters / K,
+                   "instances": len(insts), "unknowns": unknowns, "gmres_iters_per_step": iters / K,
                    "status": status},
         "roofline": {
             "bound": "hbm", "kernel": dom, "kernel_symbol": KCLASS_KERNELS.get(dom, dom),
@@ -241,7 +290,7 @@ def main():
 
     # ---- mixed FP32 operator + FP64 refinement on the same steps
     if not args.no_mixed:
-        gm = Stepper(inst, precision=R.RSFDE_MIXED)
+        gm = Stepper(insts, precision=R.RSFDE_MIXED)
         for _ in range(W):
             gm.step()
         it0 = gm.iters
@@ -251,14 +300,16 @@ def main():
             gm.step()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        diff = float((gm.u - u64).abs().max() / u64.abs().max().clamp_min(1e-300))
+        diff = max(float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+                   for a, b in zip(gm.us, u64))
         out["mixed"] = {"value": K / el, "unit": "time-steps/s", "ms_per_step": 1e3 * el / K,
                         "gmres_iters_per_step": (gm.iters - it0) / K,
                         "rel_diff_vs_fp64_gpu": diff, "status": gm.status}
         gm.close()
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_steps)
+        out["cpu_baseline"] = (cpu_baseline(inst, args.cpu_steps) if len(insts) == 1
+                               else cpu_baseline_batch(insts, args.cpu_instances))
     print(json.dumps(out), flush=True)
 
 

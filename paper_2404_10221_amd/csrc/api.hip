@@ -26,6 +26,12 @@
   hipError_t launch_pass_L<float, L>(const PassArgs&, bool, int, hipStream_t, hipEvent_t,   \
                                      hipEvent_t);                                            \
   template <>                                                                                \
+  hipError_t launch_pass_batched_L<double, L>(const BLaunch&, int64_t, bool, int, hipStream_t, \
+                                              hipEvent_t, hipEvent_t);                      \
+  template <>                                                                                \
+  hipError_t launch_pass_batched_L<float, L>(const BLaunch&, int64_t, bool, int, hipStream_t, \
+                                             hipEvent_t, hipEvent_t);                       \
+  template <>                                                                                \
   hipError_t launch_spectrum_L<L>(const double*, int, const cpx<double>*, double*, float*,  \
                                   double*, hipStream_t);
 RSFDE_FOR_EACH_L(RSFDE_DECL)
@@ -49,6 +55,20 @@ static hipError_t launch_pass(int L, bool fp32, const PassArgs& a, bool strided,
   case LL:                                                                \
     return fp32 ? launch_pass_L<float, LL>(a, strided, a.var, s, ea, eb)  \
                 : launch_pass_L<double, LL>(a, strided, a.var, s, ea, eb);
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_pass_batched(int L, bool fp32, const BLaunch& bl, int64_t nblocks,
+                                      bool strided, int var, hipStream_t s, hipEvent_t ea,
+                                      hipEvent_t eb) {
+  switch (L) {
+#define RSFDE_CASE(LL)                                                                     \
+  case LL:                                                                                 \
+    return fp32 ? launch_pass_batched_L<float, LL>(bl, nblocks, strided, var, s, ea, eb)   \
+                : launch_pass_batched_L<double, LL>(bl, nblocks, strided, var, s, ea, eb);
     RSFDE_FOR_EACH_L(RSFDE_CASE)
 #undef RSFDE_CASE
   }
@@ -158,9 +178,42 @@ struct TimedPass {
     if (s_ < 0) return s_;      \
   } while (0)
 
+// one batched launch: the instances that share a pass position's transform
+// length, precision, axis kind and tile shape
+struct BGroup {
+  int L = 0, var = 0;
+  bool fp32 = false, strided = false;
+  int ninst = 0;
+  int64_t nblocks = 0;
+  size_t desc_off = 0, start_off = 0;  // offsets in the batch descriptor buffer
+  int cls = 0;
+  double bytes = 0;
+};
+struct BChain {
+  std::vector<std::vector<BGroup>> pos;  // groups per pass position of the chain
+};
+struct RecPass {
+  PassArgs a;
+  bool fp32;
+  int inst;
+};
+
 struct rsfde_ctx {
   int count = 0;
   std::vector<Inst> inst;
+  // batched engine (count > 1)
+  bool batched = false;
+  char* bdev = nullptr;          // descriptor buffer in the workspace
+  char* bhost = nullptr;         // pinned staging copy
+  size_t bcap = 0, bfill = 0;
+  GmresSummary* dsum = nullptr;  // gathered summaries (workspace) and their pinned copy
+  GmresSummary* psum = nullptr;
+  std::vector<RecPass>* rec = nullptr;  // chain recording instead of launching
+  int rec_inst = -1;
+  struct AtEntry {
+    int fp, ax, cls, L, var;
+  };
+  std::vector<AtEntry> atc;  // batched handles: one tile variant per (precision, axis, class, L)
   hipStream_t stream = nullptr;
   GmresSummary* pinned = nullptr;
   unsigned tmask = 0;
@@ -369,6 +422,10 @@ static int op_class(int op) {
 
 static int run_pass(rsfde_ctx* h, const Inst& I, const PassArgs& a, bool fp32) {
   const int L = I.ax[a.axis].L;
+  if (h->rec) {
+    h->rec->push_back(RecPass{a, fp32, h->rec_inst});
+    return RSFDE_OK;
+  }
   if (a.ntiles <= 0) return RSFDE_OK;
   if (a.nlaunch > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
   return timed_launch(h, op_class(a.op), pass_bytes(a, I, fp32), [&](hipEvent_t ea, hipEvent_t eb) {
@@ -723,6 +780,391 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
 }
 
 // ---------------------------------------------------------------------------
+// batched engine: all instances of a handle advance together.  Each pass
+// position of a chain is one launch per group of instances sharing transform
+// length, precision, axis kind and tile shape; each Krylov sweep, the update
+// and the cycle start are one launch over all instances.  Instances keep their
+// own GMRES state and stop on their own flags; the host drops an instance from
+// the launches once its cycle has ended (its update applied exactly once).
+// ---------------------------------------------------------------------------
+static bool batchable(const rsfde_ctx* h) {
+  if (h->count < 2) return false;
+  const char* off = getenv("RSFDE_NO_BATCH");
+  if (off && off[0] == '1') return false;
+  // one chain shape and one restart length for all (the basis columns a launch
+  // addresses exist in every instance)
+  for (const Inst& I : h->inst)
+    if (I.d != h->inst[0].d || I.p.precision != h->inst[0].p.precision ||
+        I.p.restart != h->inst[0].p.restart)
+      return false;
+  return true;
+}
+
+// Descriptor buffer capacity for `count` instances: three chains of at most 7
+// pass positions, each with a descriptor and a block-start entry per instance
+// (64-byte aligned per group), plus the Krylov descriptors and their starts.
+static size_t batch_capacity(int count) {
+  const size_t per_pos = (size_t)count * (sizeof(BPass) + 3 * 64 + 8) + 64;
+  return 3 * 7 * per_pos + (size_t)count * (sizeof(KBatch) + 16) + 4 * 64 + 4096;
+}
+
+static size_t bappend(rsfde_ctx* h, const void* src, size_t bytes) {
+  const size_t off = (h->bfill + 63) & ~(size_t)63;
+  if (off + bytes > h->bcap) return (size_t)-1;
+  memcpy(h->bhost + off, src, bytes);
+  h->bfill = off + bytes;
+  return off;
+}
+
+// Plan of one chain over the instance set S: record each instance's passes
+// (same sequence of ops for every instance) and group them per position.
+template <typename RecFn>
+static int plan_chain(rsfde_ctx* h, const std::vector<int>& S, RecFn rec_one, bool oper, BChain& out) {
+  std::vector<std::vector<RecPass>> recs(S.size());
+  for (size_t s = 0; s < S.size(); ++s) {
+    h->rec = &recs[s];
+    h->rec_inst = S[s];
+    const int st = rec_one(S[s]);
+    h->rec = nullptr;
+    if (st < 0) return st;
+  }
+  const size_t P = recs.empty() ? 0 : recs[0].size();
+  for (auto& r : recs)
+    if (r.size() != P) return RSFDE_E_STATE;
+  out.pos.assign(P, {});
+  for (size_t pi = 0; pi < P; ++pi) {
+    std::vector<int> used(S.size(), 0);
+    for (size_t s0 = 0; s0 < S.size(); ++s0) {
+      if (used[s0]) continue;
+      const RecPass& r0 = recs[s0][pi];
+      const Inst& I0 = h->inst[r0.inst];
+      BGroup g;
+      g.L = I0.ax[r0.a.axis].L;
+      g.var = r0.a.var;
+      g.fp32 = r0.fp32;
+      g.strided = r0.a.axis > 0;
+      g.cls = op_class(r0.a.op);
+      std::vector<BPass> desc;
+      std::vector<int> start(1, 0);
+      for (size_t s = s0; s < S.size(); ++s) {
+        const RecPass& r = recs[s][pi];
+        const Inst& I = h->inst[r.inst];
+        if (used[s] || I.ax[r.a.axis].L != g.L || r.a.var != g.var || r.fp32 != g.fp32 ||
+            (r.a.axis > 0) != g.strided || r.a.op != r0.a.op)
+          continue;
+        used[s] = 1;
+        BPass b;
+        memset(&b, 0, sizeof(b));
+        b.a = r.a;
+        b.ldv = I.ldv;
+        if (oper) {
+          if (r.a.in_c == (const void*)I.V) b.patch |= BP_IN_J;
+          if (r.a.out_a == (void*)(I.V + I.ldv)) b.patch |= BP_OUT_J;
+          if (r.a.use_gm) b.patch |= BP_GM;
+          if (r.a.stop_fl == &I.st->FL[0]) b.patch |= BP_STOP;
+        }
+        desc.push_back(b);
+        const int64_t nb = (r.a.nlaunch + 7) / 8 * 8;  // 8-aligned: XCD order kept per instance
+        if (start.back() + nb > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
+        start.push_back((int)(start.back() + nb));
+        g.bytes += pass_bytes(r.a, I, r.fp32);
+      }
+      g.ninst = (int)desc.size();
+      g.nblocks = start.back();
+      g.desc_off = bappend(h, desc.data(), desc.size() * sizeof(BPass));
+      g.start_off = bappend(h, start.data(), start.size() * sizeof(int));
+      if (g.desc_off == (size_t)-1 || g.start_off == (size_t)-1) return RSFDE_E_WORKSPACE;
+      out.pos[pi].push_back(g);
+    }
+  }
+  return RSFDE_OK;
+}
+
+static int launch_chain_batched(rsfde_ctx* h, const BChain& c, int j, int pend) {
+  for (const auto& pos : c.pos)
+    for (const BGroup& g : pos) {
+      if (g.nblocks <= 0) continue;
+      BLaunch bl;
+      bl.desc = (const BPass*)(h->bdev + g.desc_off);
+      bl.start = (const int*)(h->bdev + g.start_off);
+      bl.ninst = g.ninst;
+      bl.j = j;
+      bl.pend = pend;
+      CKS(timed_launch(h, g.cls, g.bytes, [&](hipEvent_t ea, hipEvent_t eb) {
+        return launch_pass_batched(g.L, g.fp32, bl, g.nblocks, g.strided, g.var, h->stream, ea, eb);
+      }));
+    }
+  return RSFDE_OK;
+}
+
+struct KPlan {
+  int ninst = 0;
+  size_t desc_off = 0, start_nb_off = 0, start_nbu_off = 0;
+  int64_t nb_total = 0, nbu_total = 0;
+  double vbytes = 0;  // one FP64 vector over all instances
+  int m = 0;          // largest restart
+};
+
+static int plan_krylov(rsfde_ctx* h, const std::vector<int>& S, double* const* u, KPlan& kp) {
+  std::vector<KBatch> desc;
+  std::vector<int> snb(1, 0), snbu(1, 0);
+  kp = KPlan();
+  for (int i : S) {
+    Inst& I = h->inst[i];
+    KBatch d;
+    memset(&d, 0, sizeof(d));
+    d.k.V = I.V;
+    d.k.ldv = I.ldv;
+    d.k.n = I.n;
+    d.k.w = I.V + I.ldv;
+    d.k.st = I.st;
+    d.k.pa = I.pk[0];
+    d.k.pb = I.pk[1];
+    d.k.pc = I.pk[2];
+    d.k.j = 0;
+    d.k.m = I.p.restart;
+    d.x = u[i];
+    d.partial = I.partial;
+    d.rtol = I.p.rtol;
+    d.inner_rtol = I.p.inner_rtol > 0.0 ? I.p.inner_rtol : 1e-5;
+    d.nb = kry_blocks(I.n);
+    d.nbu = upd_blocks(I.n);
+    d.mixed = I.p.precision == RSFDE_MIXED ? 1 : 0;
+    desc.push_back(d);
+    snb.push_back(snb.back() + d.nb);
+    snbu.push_back(snbu.back() + d.nbu);
+    kp.vbytes += 8.0 * (double)I.n;
+    kp.m = std::max(kp.m, I.p.restart);
+  }
+  kp.ninst = (int)S.size();
+  kp.nb_total = snb.back();
+  kp.nbu_total = snbu.back();
+  kp.desc_off = bappend(h, desc.data(), desc.size() * sizeof(KBatch));
+  kp.start_nb_off = bappend(h, snb.data(), snb.size() * sizeof(int));
+  kp.start_nbu_off = bappend(h, snbu.data(), snbu.size() * sizeof(int));
+  if (kp.desc_off == (size_t)-1 || kp.start_nb_off == (size_t)-1 || kp.start_nbu_off == (size_t)-1)
+    return RSFDE_E_WORKSPACE;
+  return RSFDE_OK;
+}
+
+static KLaunch klaunch(const rsfde_ctx* h, const KPlan& kp, bool upd, int j, int pend, int first) {
+  KLaunch kl;
+  kl.desc = (const KBatch*)(h->bdev + kp.desc_off);
+  kl.start = (const int*)(h->bdev + (upd ? kp.start_nbu_off : kp.start_nb_off));
+  kl.ninst = kp.ninst;
+  kl.j = j;
+  kl.pend = pend;
+  kl.first = first;
+  return kl;
+}
+
+// Plans for the set S: the right-hand side chain (when rhs), the residual and
+// operator chains and the Krylov descriptors; uploaded in one copy.
+struct BPlan {
+  BChain rhs, resid, oper;
+  KPlan kp;
+};
+
+static int build_plans(rsfde_ctx* h, const std::vector<int>& S, double* const* u, bool rhs,
+                       bool fp32, BPlan& bp) {
+  CK(hipStreamSynchronize(h->stream));  // earlier copies out of the staging buffer are done
+  h->bfill = 0;
+  if (rhs)
+    CKS(plan_chain(h, S, [&](int i) {
+      Inst& I = h->inst[i];
+      return run_chain(h, I, CH_RHS, false, u[i], nullptr, I.F, I.p.dt, I.b);
+    }, false, bp.rhs));
+  CKS(plan_chain(h, S, [&](int i) {
+    Inst& I = h->inst[i];
+    return run_chain(h, I, CH_RESID, false, u[i], nullptr, I.b, 1.0, I.V);
+  }, false, bp.resid));
+  CKS(plan_chain(h, S, [&](int i) {
+    Inst& I = h->inst[i];
+    GmRes g;
+    g.st = I.st;
+    g.p3 = I.pk[2];
+    g.nb3 = kry_blocks(I.n);
+    g.j = 0;
+    g.pend = -1;
+    g.m = I.p.restart;
+    return run_chain(h, I, CH_OPER, fp32, I.V, nullptr, nullptr, 0.0, I.V + I.ldv, &g, &I.st->FL[0]);
+  }, true, bp.oper));
+  CKS(plan_krylov(h, S, u, bp.kp));
+  CK(hipMemcpyAsync(h->bdev, h->bhost, h->bfill, hipMemcpyHostToDevice, h->stream));
+  return RSFDE_OK;
+}
+
+static int read_summaries(rsfde_ctx* h, const KPlan& kp) {
+  CK(kry_gather_summaries((const KBatch*)(h->bdev + kp.desc_off), kp.ninst, h->dsum, h->stream));
+  CK(hipMemcpyAsync(h->psum, h->dsum, kp.ninst * sizeof(GmresSummary), hipMemcpyDeviceToHost,
+                    h->stream));
+  CK(hipStreamSynchronize(h->stream));
+  if (!h->pending.empty()) CKS(flush_timing(h));
+  return RSFDE_OK;
+}
+
+// One lockstep GMRES cycle over the set S (cycle start already launched); on
+// return fin[i] holds each instance's final summary of the cycle.
+static int run_cycle_batched(rsfde_ctx* h, std::vector<int> S, double* const* u, bool fp32,
+                             BPlan& bp, std::vector<GmresSummary>& fin) {
+  int kprev = 1;
+  for (int i : S) kprev = std::max(kprev, h->inst[i].k_prev);
+  int j = 0, pending = -1;
+  int chunk = std::max(1, std::min(bp.kp.m, kprev));
+  while (true) {
+    const int m = bp.kp.m;
+    const int jend = std::min(m, j + chunk);
+    for (int jj = j; jj < jend; ++jj) {
+      CKS(launch_chain_batched(h, bp.oper, jj, jj == j ? pending : jj - 1));
+      for (int w = 1; w <= 3; ++w) {
+        const KLaunch kl = klaunch(h, bp.kp, false, jj, -1, 0);
+        const int cls = w == 1 ? RSFDE_K_DOTS : (w == 2 ? RSFDE_K_ORTH_DOTS : RSFDE_K_ORTH_NORM);
+        CKS(timed_launch(h, cls, bp.kp.vbytes * (jj + 2 + (w > 1 ? 1 : 0)), [&](hipEvent_t ea, hipEvent_t eb) {
+          return kry_sweep_batched(w, kl, bp.kp.nb_total, h->stream, ea, eb);
+        }));
+      }
+    }
+    const KLaunch ku = klaunch(h, bp.kp, true, jend - 1, jend - 1, 0);
+    CKS(timed_launch(h, RSFDE_K_UPDATE, 0.0, [&](hipEvent_t ea, hipEvent_t eb) {
+      return kry_update_batched(ku, bp.kp.nbu_total, h->stream, ea, eb);
+    }));
+    CKS(read_summaries(h, bp.kp));
+    std::vector<int> run;
+    for (size_t s = 0; s < S.size(); ++s) {
+      const GmresSummary& G = h->psum[s];
+      if (G.flag == GM_RUNNING) run.push_back(S[s]);
+      else fin[S[s]] = G;
+    }
+    if (run.empty()) return RSFDE_OK;
+    j = jend;
+    pending = -1;
+    chunk = 1;
+    if (j >= bp.kp.m) return RSFDE_OK;  // cannot happen: the last step of a cycle never runs on
+    if (run.size() < S.size()) {
+      // finished instances leave the launches (their solution update is done)
+      S = run;
+      CKS(build_plans(h, S, u, false, fp32, bp));
+    }
+  }
+}
+
+static int step_batched(rsfde_ctx* h, const double* const* e_half, const double* const* f_half,
+                        double* const* u, rsfde_stats* stats) {
+  const int C = h->count;
+  const bool mixed = h->inst[0].p.precision == RSFDE_MIXED;
+  for (int i = 0; i < C; ++i) {
+    Inst& I = h->inst[i];
+    if (!I.ebar_set) return RSFDE_E_STATE;
+    if ((uintptr_t)u[i] & 15) return RSFDE_E_INVALID_ARG;
+  }
+  for (int i = 0; i < C; ++i) {
+    Inst& I = h->inst[i];
+    if (e_half[i] != I.e)
+      CK(hipMemcpyAsync(I.e, e_half[i], I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    GridDev gi = grid_dev(I, false);
+    double al[3] = {I.p.alpha[0], I.p.alpha[1], I.p.alpha[2]};
+    CK(compute_F(f_half[i], gi, al, I.F, h->stream));
+    if (mixed) CK(convert_f64_f32(I.e, I.e32, I.n, h->stream));
+  }
+  std::vector<int> act(C);
+  for (int i = 0; i < C; ++i) act[i] = i;
+  BPlan bp;
+  CKS(build_plans(h, act, u, true, mixed, bp));
+  CKS(launch_chain_batched(h, bp.rhs, 0, -1));
+  for (int i = 0; i < C; ++i)
+    if (h->inst[i].p.x0_mode == 1) CK(fill_f64(u[i], h->inst[i].n, 0.0, h->stream));
+  std::vector<int> status(C, RSFDE_W_NOT_CONVERGED);
+  std::vector<rsfde_stats> st(C);
+  memset(st.data(), 0, sizeof(rsfde_stats) * C);
+  std::vector<GmresSummary> last(C);
+  memset(last.data(), 0, sizeof(GmresSummary) * C);
+  for (int cyc = 0; !act.empty(); ++cyc) {
+    if (cyc > 0) CKS(build_plans(h, act, u, false, mixed, bp));
+    CKS(launch_chain_batched(h, bp.resid, 0, -1));
+    {
+      const KLaunch kl = klaunch(h, bp.kp, false, 0, -1, cyc == 0 ? 1 : 0);
+      CK(kry_norm_batched(kl, bp.kp.nb_total, h->stream));
+      CK(kry_cycle_fin_batched(kl, h->stream));
+    }
+    std::vector<int> go;  // instances that run a cycle now
+    if (mixed) {
+      // instances at their last outer sweep only check the refined residual
+      bool any_final = false;
+      for (int i : act) {
+        const int max_outer = h->inst[i].p.max_outer > 0 ? h->inst[i].p.max_outer : 30;
+        if (cyc == max_outer) any_final = true;
+      }
+      if (any_final) {
+        CKS(read_summaries(h, bp.kp));
+        for (size_t s = 0; s < act.size(); ++s) {
+          const int i = act[s];
+          const int max_outer = h->inst[i].p.max_outer > 0 ? h->inst[i].p.max_outer : 30;
+          if (cyc == max_outer) {
+            last[i] = h->psum[s];
+            if (h->psum[s].flag == GM_CONVERGED) status[i] = RSFDE_OK;
+          } else {
+            go.push_back(i);
+          }
+        }
+        if (go.size() < act.size() && !go.empty()) CKS(build_plans(h, go, u, false, mixed, bp));
+      } else {
+        go = act;
+      }
+    } else {
+      go = act;
+    }
+    if (go.empty()) break;
+    std::vector<GmresSummary> fin(C);
+    memset(fin.data(), 0, sizeof(GmresSummary) * C);
+    CKS(run_cycle_batched(h, go, u, mixed, bp, fin));
+    std::vector<int> next;
+    for (int i : go) {
+      Inst& I = h->inst[i];
+      const GmresSummary& S = fin[i];
+      last[i] = S;
+      if (S.flag == GM_NONFINITE) return RSFDE_E_NONFINITE;
+      st[i].iters += S.k;
+      if (S.k > 0) {
+        st[i].cycles += 1;
+        I.k_prev = S.k;
+      }
+      bool done = false;
+      if (mixed) {
+        if (S.k == 0 && S.flag == GM_CONVERGED) {
+          status[i] = RSFDE_OK;
+          done = true;
+        } else {
+          st[i].outer_sweeps += 1;
+        }
+      } else {
+        if (S.flag == GM_CONVERGED || S.flag == GM_BREAKDOWN) {
+          status[i] = RSFDE_OK;
+          done = true;
+        } else if (cyc + 1 >= I.p.max_cycles) {
+          done = true;
+        }
+      }
+      if (!done) next.push_back(i);
+    }
+    act = next;
+  }
+  int worst = RSFDE_OK;
+  for (int i = 0; i < C; ++i) {
+    if (stats) {
+      rsfde_stats& o = stats[i];
+      o.iters += st[i].iters;
+      o.cycles += st[i].cycles;
+      o.outer_sweeps += st[i].outer_sweeps;
+      o.converged = status[i] == RSFDE_OK ? 1 : 0;
+      o.beta0 = last[i].beta0;
+      o.rel_pres = last[i].beta0 > 0 ? (mixed ? last[i].beta : last[i].res) / last[i].beta0 : 0.0;
+    }
+    worst = std::max(worst, status[i]);
+  }
+  return worst;
+}
+
+// ---------------------------------------------------------------------------
 // tile autotuner: time the workgroup-shape variants of every pass kind the
 // chains use (operator pass and transform pass, per axis and precision) on the
 // instance's own grid and keep the fastest.  The variants only change how many
@@ -762,9 +1204,20 @@ static int autotune(rsfde_ctx* h, Inst& I) {
         // variants interleaved over three rounds, each timing two launches whose
         // inputs and outputs rotate over the four temporaries (inputs are not
         // left cache-resident by the previous launch); the best round counts
+        const int L = I.ax[ax].L;
+        if (h->count > 1) {
+          // instances of one handle share a variant per (precision, axis, class, L),
+          // so that batched launches group them
+          int cached = -1;
+          for (const auto& e : h->atc)
+            if (e.fp == fp && e.ax == ax && e.cls == cls && e.L == L) cached = e.var;
+          if (cached >= 0) {
+            I.var[ax][fp][cls] = cached;
+            continue;
+          }
+        }
         float tbest[RSFDE_PASS_VARIANTS];
         for (int v = 0; v < RSFDE_PASS_VARIANTS; ++v) tbest[v] = 1e30f;
-        const int L = I.ax[ax].L;
         for (int rep = 0; rep < 3 && status == RSFDE_OK; ++rep) {
           for (int v = 0; v < RSFDE_PASS_VARIANTS && status == RSFDE_OK; ++v) {
             I.var[ax][fp][cls] = v;
@@ -799,6 +1252,7 @@ static int autotune(rsfde_ctx* h, Inst& I) {
                   ax, fp ? "fp32" : "fp64", cls ? "transform" : "operator", 500.f * tbest[0],
                   500.f * tbest[1], 500.f * tbest[2], bestv);
         I.var[ax][fp][cls] = bestv;
+        if (h->count > 1) h->atc.push_back(rsfde_ctx::AtEntry{fp, ax, cls, L, bestv});
       }
     }
   }
@@ -822,6 +1276,10 @@ int rsfde_workspace_size(const rsfde_params* p, int count, size_t* bytes) {
     I.p = p[i];
     layout(I, B);
   }
+  if (count > 1) {
+    (void)B.take<char>(batch_capacity(count));
+    (void)B.take<GmresSummary>((size_t)count);
+  }
   *bytes = (B.off + 255) & ~(size_t)255;
   return RSFDE_OK;
 }
@@ -841,8 +1299,16 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
   Bump B{(char*)workspace};
   int status = RSFDE_OK;
   hipError_t he = hipHostMalloc((void**)&h->pinned, sizeof(GmresSummary), hipHostMallocDefault);
+  if (he == hipSuccess && count > 1) {
+    h->bcap = batch_capacity(count);
+    he = hipHostMalloc((void**)&h->bhost, h->bcap, hipHostMallocDefault);
+    if (he == hipSuccess)
+      he = hipHostMalloc((void**)&h->psum, (size_t)count * sizeof(GmresSummary), hipHostMallocDefault);
+  }
   if (he != hipSuccess) {
     g_last_hip = he;
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->bhost) (void)hipHostFree(h->bhost);
     delete h;
     return RSFDE_E_HIP;
   }
@@ -886,6 +1352,11 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
       }
     }
   }
+  if (status == RSFDE_OK && count > 1) {
+    h->bdev = B.take<char>(h->bcap);
+    h->dsum = B.take<GmresSummary>((size_t)count);
+    h->batched = batchable(h);
+  }
   if (status == RSFDE_OK) {
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -896,6 +1367,8 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
   for (int i = 0; i < count && status == RSFDE_OK; ++i) status = autotune(h, h->inst[i]);
   if (status != RSFDE_OK) {
     (void)hipHostFree(h->pinned);
+    if (h->bhost) (void)hipHostFree(h->bhost);
+    if (h->psum) (void)hipHostFree(h->psum);
     delete h;
     return status;
   }
@@ -921,11 +1394,16 @@ int rsfde_step(rsfde_handle h, double t_m, const double* const* e_half, const do
   for (int i = 0; i < h->count; ++i)
     if (!e_half[i] || !f_half[i] || !u[i]) return RSFDE_E_INVALID_ARG;
   int worst = RSFDE_OK;
-  for (int i = 0; i < h->count; ++i) {
-    if (stats) memset(&stats[i], 0, sizeof(rsfde_stats));
-    const int s = step_one(h, h->inst[i], e_half[i], f_half[i], u[i], stats ? &stats[i] : nullptr);
-    if (s < 0) return s;
-    if (s > worst) worst = s;
+  if (stats) memset(stats, 0, sizeof(rsfde_stats) * h->count);
+  if (h->batched) {
+    worst = step_batched(h, e_half, f_half, u, stats);
+    if (worst < 0) return worst;
+  } else {
+    for (int i = 0; i < h->count; ++i) {
+      const int s = step_one(h, h->inst[i], e_half[i], f_half[i], u[i], stats ? &stats[i] : nullptr);
+      if (s < 0) return s;
+      if (s > worst) worst = s;
+    }
   }
   CK(hipStreamSynchronize(h->stream));
   return worst;
@@ -974,7 +1452,36 @@ int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx, double
     CKS(rsfde_set_ebar(h, i, mm[0], mm[1]));
   }
   int worst = RSFDE_OK;
+  std::vector<const double*> ep(h->count), fp(h->count);
+  std::vector<rsfde_stats> sb(h->count);
   for (int m = 0; m < M; ++m) {
+    if (h->batched) {
+      for (int i = 0; i < h->count; ++i) {
+        Inst& I = h->inst[i];
+        const double th = (m + 0.5) * I.p.dt;
+        if (sample) {
+          if (sample(ctx, i, th, I.e, I.f, (void*)h->stream) != 0) return RSFDE_E_INVALID_ARG;
+        } else {
+          CKS(builtin_sample(h, I, th, true));
+        }
+        ep[i] = I.e;
+        fp[i] = I.f;
+      }
+      memset(sb.data(), 0, sizeof(rsfde_stats) * h->count);
+      const int s = step_batched(h, ep.data(), fp.data(), u, sb.data());
+      if (s < 0) return s;
+      if (s > worst) worst = s;
+      if (stats)
+        for (int i = 0; i < h->count; ++i) {
+          stats[i].iters += sb[i].iters;
+          stats[i].cycles += sb[i].cycles;
+          stats[i].outer_sweeps += sb[i].outer_sweeps;
+          stats[i].converged = (m == 0 ? 1 : stats[i].converged) & sb[i].converged;
+          stats[i].beta0 = sb[i].beta0;
+          stats[i].rel_pres = sb[i].rel_pres;
+        }
+      continue;
+    }
     for (int i = 0; i < h->count; ++i) {
       Inst& I = h->inst[i];
       const double th = (m + 0.5) * I.p.dt;
@@ -1011,6 +1518,8 @@ int rsfde_destroy(rsfde_handle h) {
   }
   for (auto ev : h->ev_free) (void)hipEventDestroy(ev);
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->bhost) (void)hipHostFree(h->bhost);
+  if (h->psum) (void)hipHostFree(h->psum);
   delete h;
   return RSFDE_OK;
 }

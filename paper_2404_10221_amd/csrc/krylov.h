@@ -141,7 +141,8 @@ __device__ __forceinline__ void gm_fetch(const GmRes& g, GmIn& in) {
 // from their lanes, followed by the new Givens rotation and the stopping test
 // (Lemma Krylov: |g_{j+1}| is the residual norm of the least-squares problem).
 // On return `o` (shared) holds the status and `col` the resolved column.
-__device__ __forceinline__ void gm_resolve(const GmRes& g, const GmIn& in, GmOut* o, GmCol* col) {
+__device__ __forceinline__ void gm_resolve(const GmRes& g, const GmIn& in, GmOut* o, GmCol* col,
+                                           bool writer) {
   GmresState* st = g.st;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
@@ -202,7 +203,7 @@ __device__ __forceinline__ void gm_resolve(const GmRes& g, const GmIn& in, GmOut
       else flag = GM_RUNNING;
       const bool fin = flag != GM_RUNNING && flag != GM_NONFINITE;
       if (lane <= j) col->rc[lane] = rcl;
-      if (blockIdx.x == 0) {
+      if (writer) {
         constexpr int MX = RSFDE_MAX_RESTART;
         if (lane <= j) st->Rm[j * MX + lane] = rcl;
         if (lane == 0) {
@@ -233,10 +234,23 @@ __device__ __forceinline__ void gm_resolve(const GmRes& g, const GmIn& in, GmOut
 }
 
 // Fetch and resolve (for kernels with nothing to overlap the fetch with).
-__device__ __forceinline__ void gm_prologue(const GmRes& g, GmOut* o, GmCol* col) {
+__device__ __forceinline__ void gm_prologue(const GmRes& g, GmOut* o, GmCol* col, bool writer) {
   GmIn in;
   if (threadIdx.x < 64) gm_fetch(g, in);
-  gm_resolve(g, in, o, col);
+  gm_resolve(g, in, o, col, writer);
+}
+
+// Slot of block `bid`: the number of slots s >= 1 with start[s] <= bid (one
+// ballot per 64 slots, identical in every wavefront).
+__device__ __forceinline__ int batch_slot(const int* __restrict__ start, int n, int bid) {
+  int slot = 0;
+  const int lane = threadIdx.x & 63;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + lane;
+    const bool le = i < n && start[i + 1] <= bid;
+    slot += __popcll(__ballot(le));
+  }
+  return __builtin_amdgcn_readfirstlane(slot);
 }
 
 struct KryArgs {
@@ -252,6 +266,33 @@ struct KryArgs {
   int m;              // restart length
 };
 
+// Blocks of the solution-update kernel for an n-vector.
+inline int upd_blocks(int64_t n) {
+  int64_t b = (n / 2 + 1023) / 1024;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// ---- batched Krylov launches: per-instance arguments in device memory, the
+// instance of a block from the block prefix sums (as for the batched passes).
+struct KBatch {
+  KryArgs k;           // as for Arnoldi step 0 (w = column 1); j and w follow the launch
+  double* x;           // solution the update kernel adds V y to
+  double* partial;     // cycle-start norm partials
+  double rtol, inner_rtol;
+  int nb;              // blocks of this instance's sweeps and norm (kry_blocks(n))
+  int nbu;             // blocks of this instance's update (upd_blocks(n))
+  int mixed;
+  int pad;
+};
+struct KLaunch {
+  const KBatch* desc;  // slot order
+  const int* start;    // block prefix sums of the launch (per-instance block counts)
+  int ninst;
+  int j, pend, first;
+};
+
 // Launchers (krylov.hip)
 hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial, int first,
                           double rtol, double inner_rtol, int mixed, int m, hipStream_t s);
@@ -261,3 +302,13 @@ hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea =
 hipError_t kry_update(const double* V, int64_t ldv, int64_t n, double* x, const GmRes& g,
                       hipStream_t s, hipEvent_t ea = nullptr, hipEvent_t eb = nullptr);
 hipError_t kry_state_reset(GmresState* st, hipStream_t s);
+// batched forms: `nblocks` = start[ninst]; sweeps and norms use KBatch::nb blocks
+// per instance, the update KBatch::nbu, the cycle-start finish one block per instance
+hipError_t kry_sweep_batched(int which, const KLaunch& kl, int64_t nblocks, hipStream_t s,
+                             hipEvent_t ea = nullptr, hipEvent_t eb = nullptr);
+hipError_t kry_update_batched(const KLaunch& kl, int64_t nblocks, hipStream_t s,
+                              hipEvent_t ea = nullptr, hipEvent_t eb = nullptr);
+hipError_t kry_norm_batched(const KLaunch& kl, int64_t nblocks, hipStream_t s);
+hipError_t kry_cycle_fin_batched(const KLaunch& kl, hipStream_t s);
+// out[i] = summary of slot i (desc in device memory, n slots)
+hipError_t kry_gather_summaries(const KBatch* desc, int n, GmresSummary* out, hipStream_t s);

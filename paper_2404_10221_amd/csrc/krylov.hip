@@ -49,26 +49,31 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
 }
 
 // ---- ||v||^2 partials and cycle start -------------------------------------------------
-__global__ void __launch_bounds__(1024)
-k_norm_part(const double* __restrict__ v0, int64_t n, double* __restrict__ partial) {
+__device__ __forceinline__ void norm_part_body(const double* __restrict__ v0, int64_t n,
+                                               double* __restrict__ partial, int bid, int nblk) {
   double acc[1] = {0.0};
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)nblk * blockDim.x;
   const double2* __restrict__ v2 = (const double2*)v0;
   const int64_t n2 = n >> 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n2; i += stride) {
     const double2 x = v2[i];
     acc[0] += x.x * x.x + x.y * x.y;
   }
-  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) acc[0] += v0[n - 1] * v0[n - 1];
+  if ((n & 1) && bid == 0 && threadIdx.x == 0) acc[0] += v0[n - 1] * v0[n - 1];
   __shared__ double res[1];
   block_sums<1, 1024>(acc, 1, res);
-  if (threadIdx.x == 0) partial[blockIdx.x] = res[0];
+  if (threadIdx.x == 0) partial[bid] = res[0];
+}
+
+__global__ void __launch_bounds__(1024)
+k_norm_part(const double* __restrict__ v0, int64_t n, double* __restrict__ partial) {
+  norm_part_body(v0, n, partial, blockIdx.x, gridDim.x);
 }
 
 // beta = ||v0||, gamma_0 = beta, vsc[0] = 1/beta, FL[0] = status, FL[1..m] unset
-__global__ void __launch_bounds__(256)
-k_cycle_init_fin(const double* __restrict__ partial, int nblocks, GmresState* st, int first,
-                 double rtol, double inner_rtol, int mixed, int m) {
+__device__ __forceinline__ void cycle_init_body(const double* __restrict__ partial, int nblocks,
+                                                GmresState* st, int first, double rtol,
+                                                double inner_rtol, int mixed, int m) {
   __shared__ double res[1];
   reduce_partials<1, 256>(partial, nblocks, 1, res);
   if ((int)threadIdx.x >= 1 && (int)threadIdx.x <= m) st->FL[threadIdx.x] = GM_UNSET;
@@ -93,9 +98,15 @@ k_cycle_init_fin(const double* __restrict__ partial, int nblocks, GmresState* st
   }
 }
 
+__global__ void __launch_bounds__(256)
+k_cycle_init_fin(const double* __restrict__ partial, int nblocks, GmresState* st, int first,
+                 double rtol, double inner_rtol, int mixed, int m) {
+  cycle_init_body(partial, nblocks, st, first, rtol, inner_rtol, mixed, m);
+}
+
 // ---- CGS2 sweep 1: partials of Vbar^T w ---------------------------------------------------
 template <int KM>
-__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep1(const KryArgs a) {
+__device__ __forceinline__ void sweep1_body(const KryArgs& a, int bid, int nblk) {
   constexpr int NT = SweepNT<KM>::value;
   if (a.st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
@@ -104,11 +115,11 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep1(const KryArgs a) 
   for (int k = 0; k < KM; ++k) acc[k] = 0.0;
   const double* __restrict__ w = a.w;
   const double* __restrict__ V = a.V;
-  const int64_t stride = (int64_t)gridDim.x * NT;
+  const int64_t stride = (int64_t)nblk * NT;
   const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
   const double2* __restrict__ w2 = (const double2*)w;
   const double2* __restrict__ V2 = (const double2*)V;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n2; i += stride) {
+  for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
     const double2 wi = w2[i];
 #pragma unroll
     for (int k = 0; k < KM; ++k)
@@ -117,29 +128,34 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep1(const KryArgs a) 
         acc[k] += v.x * wi.x + v.y * wi.y;
       }
   }
-  if ((a.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+  if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
     for (int k = 0; k < KM; ++k)
       if (k < nv) acc[k] += V[k * a.ldv + i] * w[i];
   }
   __shared__ double res[KM];
   block_sums<KM, NT>(acc, nv, res);
-  if ((int)threadIdx.x < nv) a.pa[threadIdx.x * RSFDE_PVS + blockIdx.x] = res[threadIdx.x];
+  if ((int)threadIdx.x < nv) a.pa[threadIdx.x * RSFDE_PVS + bid] = res[threadIdx.x];
+}
+
+template <int KM>
+__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep1(const KryArgs a) {
+  sweep1_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
 // ---- CGS2 sweep 2: h = Vbar^T w / |v| ; w -= V h ; partials of Vbar^T w ------------------
 template <int KM>
-__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep2(const KryArgs a) {
+__device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk) {
   constexpr int NT = SweepNT<KM>::value;
   GmresState* st = a.st;
   if (st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
   __shared__ double cf[KM];
-  reduce_partials<KM, NT>(a.pa, gridDim.x, nv, cf);
+  reduce_partials<KM, NT>(a.pa, nblk, nv, cf);
   if ((int)threadIdx.x < nv) {
     const double sc = st->vsc[threadIdx.x];
     const double h = cf[threadIdx.x] * sc;
-    if (blockIdx.x == 0) st->h[threadIdx.x] = h;
+    if (bid == 0) st->h[threadIdx.x] = h;
     cf[threadIdx.x] = h * sc;
   }
   __syncthreads();
@@ -148,11 +164,11 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep2(const KryArgs a) 
   for (int k = 0; k < KM; ++k) acc[k] = 0.0;
   double* __restrict__ w = a.w;
   const double* __restrict__ V = a.V;
-  const int64_t stride = (int64_t)gridDim.x * NT;
+  const int64_t stride = (int64_t)nblk * NT;
   const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
   double2* __restrict__ w2 = (double2*)w;
   const double2* __restrict__ V2 = (const double2*)V;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n2; i += stride) {
+  for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
     double2 wi = w2[i];
     constexpr int KR = KM <= 16 ? KM : 1;  // basis values kept in registers
     double2 vk[KR];
@@ -174,7 +190,7 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep2(const KryArgs a) 
         acc[k] += v.x * wi.x + v.y * wi.y;
       }
   }
-  if ((a.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+  if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
     double wi = w[i];
     for (int k = 0; k < KM; ++k)
@@ -185,33 +201,38 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep2(const KryArgs a) 
   }
   __shared__ double res[KM];
   block_sums<KM, NT>(acc, nv, res);
-  if ((int)threadIdx.x < nv) a.pb[threadIdx.x * RSFDE_PVS + blockIdx.x] = res[threadIdx.x];
+  if ((int)threadIdx.x < nv) a.pb[threadIdx.x * RSFDE_PVS + bid] = res[threadIdx.x];
+}
+
+template <int KM>
+__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep2(const KryArgs a) {
+  sweep2_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
 // ---- CGS2 sweep 3: h2 = Vbar^T w / |v| ; w -= V h2 ; partials of ||w||^2 -----------------
 template <int KM>
-__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep3(const KryArgs a) {
+__device__ __forceinline__ void sweep3_body(const KryArgs& a, int bid, int nblk) {
   constexpr int NT = SweepNT<KM>::value;
   GmresState* st = a.st;
   if (st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
   __shared__ double cf[KM];
-  reduce_partials<KM, NT>(a.pb, gridDim.x, nv, cf);
+  reduce_partials<KM, NT>(a.pb, nblk, nv, cf);
   if ((int)threadIdx.x < nv) {
     const double sc = st->vsc[threadIdx.x];
     const double h2 = cf[threadIdx.x] * sc;
-    if (blockIdx.x == 0) st->h2[threadIdx.x] = h2;
+    if (bid == 0) st->h2[threadIdx.x] = h2;
     cf[threadIdx.x] = h2 * sc;
   }
   __syncthreads();
   double acc[1] = {0.0};
   double* __restrict__ w = a.w;
   const double* __restrict__ V = a.V;
-  const int64_t stride = (int64_t)gridDim.x * NT;
+  const int64_t stride = (int64_t)nblk * NT;
   const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
   double2* __restrict__ w2 = (double2*)w;
   const double2* __restrict__ V2 = (const double2*)V;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n2; i += stride) {
+  for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
     double2 wi = w2[i];
 #pragma unroll
     for (int k = 0; k < KM; ++k)
@@ -223,7 +244,7 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep3(const KryArgs a) 
     w2[i] = wi;
     acc[0] += wi.x * wi.x + wi.y * wi.y;
   }
-  if ((a.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+  if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
     double wi = w[i];
     for (int k = 0; k < KM; ++k)
@@ -233,20 +254,24 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep3(const KryArgs a) 
   }
   __shared__ double res[1];
   block_sums<1, NT>(acc, 1, res);
-  if (threadIdx.x == 0) a.pc[blockIdx.x] = res[0];
+  if (threadIdx.x == 0) a.pc[bid] = res[0];
+}
+
+template <int KM>
+__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep3(const KryArgs a) {
+  sweep3_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
 // ---- resolve the last launched step; x += V y when the cycle has finished ----------------
-__global__ void __launch_bounds__(256)
-k_update(const double* __restrict__ V, int64_t ldv, int64_t n, double* __restrict__ x,
-         const GmRes g) {
+__device__ __forceinline__ void update_body(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                            double* __restrict__ x, const GmRes& g, int bid, int nblk) {
   constexpr int MX = RSFDE_MAX_RESTART;
   __shared__ GmOut o;
   __shared__ GmCol col;
   __shared__ double Rs[MX * MX];  // R(i, l) at [l * MX + i], columns l < k
   __shared__ double gs[MX];
   __shared__ double cf[MX];
-  gm_prologue(g, &o, &col);
+  gm_prologue(g, &o, &col, bid == 0);
   const int flag = o.flag, k = o.k;
   if (flag == GM_RUNNING || flag == GM_NONFINITE || k <= 0) return;
   // stage the triangular factor and the rotated right-hand side: column k-1 comes
@@ -270,11 +295,11 @@ k_update(const double* __restrict__ V, int64_t ldv, int64_t n, double* __restric
     }
   }
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)nblk * blockDim.x;
   const int64_t n2 = n >> 1, ld2 = ldv >> 1;
   double2* __restrict__ x2 = (double2*)x;
   const double2* __restrict__ V2 = (const double2*)V;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n2; i += stride) {
     double2 xi = x2[i];
     for (int l = 0; l < k; ++l) {
       const double2 v = V2[l * ld2 + i];
@@ -283,11 +308,17 @@ k_update(const double* __restrict__ V, int64_t ldv, int64_t n, double* __restric
     }
     x2[i] = xi;
   }
-  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+  if ((n & 1) && bid == 0 && threadIdx.x == 0) {
     double xi = x[n - 1];
     for (int l = 0; l < k; ++l) xi += cf[l] * V[l * ldv + n - 1];
     x[n - 1] = xi;
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_update(const double* __restrict__ V, int64_t ldv, int64_t n, double* __restrict__ x,
+         const GmRes g) {
+  update_body(V, ldv, n, x, g, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_state_reset(GmresState* st) {
@@ -332,10 +363,95 @@ hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea, 
 
 hipError_t kry_update(const double* V, int64_t ldv, int64_t n, double* x, const GmRes& g,
                       hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
-  int64_t nb = (n / 2 + 1023) / 1024;
-  if (nb > 1024) nb = 1024;
-  if (nb < 1) nb = 1;
+  const int nb = upd_blocks(n);
   hipExtLaunchKernelGGL(k_update, dim3((unsigned)nb), dim3(256), 0, s, ea, eb, 0, V, ldv, n, x, g);
+  return hipGetLastError();
+}
+
+// ---- batched kernels ---------------------------------------------------------------------
+__device__ __forceinline__ KryArgs kb_args(const KBatch& d, int j) {
+  KryArgs a = d.k;
+  a.j = j;
+  a.w = d.k.w + (int64_t)j * d.k.ldv;
+  return a;
+}
+
+template <int W, int KM>
+__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep_b(const KLaunch kl) {
+  const int slot = batch_slot(kl.start, kl.ninst, blockIdx.x);
+  const KBatch& d = kl.desc[slot];
+  const KryArgs a = kb_args(d, kl.j);
+  const int bid = (int)blockIdx.x - kl.start[slot];
+  if constexpr (W == 1) sweep1_body<KM>(a, bid, d.nb);
+  else if constexpr (W == 2) sweep2_body<KM>(a, bid, d.nb);
+  else sweep3_body<KM>(a, bid, d.nb);
+}
+
+__global__ void __launch_bounds__(256) k_update_b(const KLaunch kl) {
+  const int slot = batch_slot(kl.start, kl.ninst, blockIdx.x);
+  const KBatch& d = kl.desc[slot];
+  GmRes g;
+  g.st = d.k.st;
+  g.p3 = d.k.pc;
+  g.nb3 = d.nb;
+  g.j = kl.j;
+  g.pend = kl.pend;
+  g.m = d.k.m;
+  update_body(d.k.V, d.k.ldv, d.k.n, d.x, g, (int)blockIdx.x - kl.start[slot], d.nbu);
+}
+
+__global__ void __launch_bounds__(1024) k_norm_part_b(const KLaunch kl) {
+  const int slot = batch_slot(kl.start, kl.ninst, blockIdx.x);
+  const KBatch& d = kl.desc[slot];
+  norm_part_body(d.k.V, d.k.n, d.partial, (int)blockIdx.x - kl.start[slot], d.nb);
+}
+
+__global__ void __launch_bounds__(256) k_cycle_init_fin_b(const KLaunch kl) {
+  const KBatch& d = kl.desc[blockIdx.x];
+  cycle_init_body(d.partial, d.nb, d.k.st, kl.first, d.rtol, d.inner_rtol, d.mixed, d.k.m);
+}
+
+#define KRY_SWEEP_B(W, nv, g, kl, s)                                                              \
+  do {                                                                                            \
+    if ((nv) <= 8) hipExtLaunchKernelGGL((k_sweep_b<W, 8>), g, dim3(SweepNT<8>::value), 0, s, ea, eb, 0, kl); \
+    else if ((nv) <= 16) hipExtLaunchKernelGGL((k_sweep_b<W, 16>), g, dim3(SweepNT<16>::value), 0, s, ea, eb, 0, kl); \
+    else if ((nv) <= 32) hipExtLaunchKernelGGL((k_sweep_b<W, 32>), g, dim3(SweepNT<32>::value), 0, s, ea, eb, 0, kl); \
+    else hipExtLaunchKernelGGL((k_sweep_b<W, 64>), g, dim3(SweepNT<64>::value), 0, s, ea, eb, 0, kl); \
+  } while (0)
+
+hipError_t kry_sweep_batched(int which, const KLaunch& kl, int64_t nblocks, hipStream_t s,
+                             hipEvent_t ea, hipEvent_t eb) {
+  const int nv = kl.j + 1;
+  const dim3 g((unsigned)nblocks);
+  if (which == 1) KRY_SWEEP_B(1, nv, g, kl, s);
+  else if (which == 2) KRY_SWEEP_B(2, nv, g, kl, s);
+  else KRY_SWEEP_B(3, nv, g, kl, s);
+  return hipGetLastError();
+}
+
+hipError_t kry_update_batched(const KLaunch& kl, int64_t nblocks, hipStream_t s, hipEvent_t ea,
+                              hipEvent_t eb) {
+  hipExtLaunchKernelGGL(k_update_b, dim3((unsigned)nblocks), dim3(256), 0, s, ea, eb, 0, kl);
+  return hipGetLastError();
+}
+
+hipError_t kry_norm_batched(const KLaunch& kl, int64_t nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_part_b, dim3((unsigned)nblocks), dim3(1024), 0, s, kl);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_sum(const KBatch* __restrict__ desc, int n, GmresSummary* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = desc[i].k.st->sum;
+}
+
+hipError_t kry_gather_summaries(const KBatch* desc, int n, GmresSummary* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_sum, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, desc, n, out);
+  return hipGetLastError();
+}
+
+hipError_t kry_cycle_fin_batched(const KLaunch& kl, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_init_fin_b, dim3((unsigned)kl.ninst), dim3(256), 0, s, kl);
   return hipGetLastError();
 }
 

@@ -110,11 +110,10 @@ struct PassShape {
   static constexpr int NT = F * T;
 };
 
-// Register budget of 128 VGPRs (4 waves per SIMD): measured faster on HBM-bound
-// grids than the unconstrained allocation (3 waves per SIMD) despite a few spills.
+// The pass on one tile; `bid` is the workgroup's index within the pass (the
+// block index of a single-instance launch, the local index in a batched one).
 template <typename R, int L, int F, bool STRIDED>
-__global__ void __launch_bounds__(F * FftPlan<L>::T) __attribute__((amdgpu_waves_per_eu(4)))
-rsfde_pass_kernel(const PassArgs a) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) {
   using P = FftPlan<L>;
   constexpr int T = P::T, E = P::E, NT = F * T, PT = 2 * F;
   // sequences 64 bytes apart modulo 256 (strided tiles spread over the banks)
@@ -136,12 +135,12 @@ rsfde_pass_kernel(const PassArgs a) {
   // ---- tile geometry.  Blocks are dispatched round-robin over the 8 XCDs
   // (each with its own L2); for strided passes every XCD takes a contiguous run
   // of tiles, so neighbouring tiles (which share cache lines) meet in one L2.
-  int64_t tile = blockIdx.x;
+  int64_t tile = bid;
   if (a.xcd_remap) {
-    const int64_t b = blockIdx.x, tpx = (a.ntiles + 7) >> 3;
+    const int64_t b = bid, tpx = (a.ntiles + 7) >> 3;
     tile = (b & 7) * tpx + (b >> 3);
-    if (tile >= a.ntiles) return;
   }
+  if (tile >= a.ntiles) return;  // launches are rounded up to whole XCD rounds
   int64_t row0 = 0, gbase = 0;
   int nvalid;
   if constexpr (!STRIDED) {
@@ -255,7 +254,7 @@ rsfde_pass_kernel(const PassArgs a) {
   if (a.use_gm) {
     __shared__ GmOut go;
     __shared__ GmCol gcol;
-    gm_resolve(a.gm, gin, &go, &gcol);
+    gm_resolve(a.gm, gin, &go, &gcol, bid == 0);
     if (go.flag != GM_RUNNING) return;  // same value in every thread
     sc = (R)go.sc;
   } else {
@@ -607,12 +606,60 @@ rsfde_pass_kernel(const PassArgs a) {
   }
 }
 
+// Register budget of 128 VGPRs (4 waves per SIMD): measured faster on HBM-bound
+// grids than the unconstrained allocation (3 waves per SIMD) despite a few spills.
+template <typename R, int L, int F, bool STRIDED>
+__global__ void __launch_bounds__(F * FftPlan<L>::T) __attribute__((amdgpu_waves_per_eu(4)))
+rsfde_pass_kernel(const PassArgs a) {
+  pass_body<R, L, F, STRIDED>(a, blockIdx.x);
+}
+
+// ---- batched passes: one launch covers the same pass of many instances that
+// share the transform length and tile shape.  Each instance's arguments sit in
+// device memory; the fields that move with the Arnoldi index j are patched in
+// the kernel from the launch's j (the basis column read or written, the step of
+// the Givens resolve, the status word that stops speculative launches).
+enum : int { BP_IN_J = 1, BP_OUT_J = 2, BP_GM = 4, BP_STOP = 8 };
+struct BPass {
+  PassArgs a;    // arguments as for Arnoldi step 0
+  int64_t ldv;   // basis leading dimension (element offset per step)
+  int patch;     // BP_* bits
+  int pad;
+};
+struct BLaunch {
+  const BPass* desc;   // per-instance descriptors of this launch, slot order
+  const int* start;    // start[s] = first block of slot s; start[ninst] = grid size
+  int ninst;
+  int j, pend;         // Arnoldi step and pending resolve of this launch
+};
+
+template <typename R, int L, int F, bool STRIDED>
+__global__ void __launch_bounds__(F * FftPlan<L>::T) __attribute__((amdgpu_waves_per_eu(4)))
+rsfde_pass_batched(const BLaunch bl) {
+  const int slot = batch_slot(bl.start, bl.ninst, blockIdx.x);
+  const BPass& d = bl.desc[slot];
+  PassArgs a = d.a;
+  const int64_t jo = (int64_t)bl.j * d.ldv;
+  if (d.patch & BP_IN_J) a.in_c = (const double*)a.in_c + jo;
+  if (d.patch & BP_OUT_J) a.out_a = (double*)a.out_a + jo;
+  if (d.patch & BP_GM) {
+    a.gm.j = bl.j;
+    a.gm.pend = bl.pend;
+  }
+  if (d.patch & BP_STOP) a.stop_fl = a.stop_fl + bl.j;
+  pass_body<R, L, F, STRIDED>(a, (int64_t)blockIdx.x - bl.start[slot]);
+}
+
 // Host launcher for one (precision, length); defined in the per-length
 // instantiation units.  Returns a hipError_t.
 // ea/eb: when non-null, HIP events stamped at the dispatch's start and end.
 template <typename R, int L>
 hipError_t launch_pass_L(const PassArgs& a, bool strided, int var, hipStream_t s, hipEvent_t ea,
                          hipEvent_t eb);
+
+template <typename R, int L>
+hipError_t launch_pass_batched_L(const BLaunch& bl, int64_t nblocks, bool strided, int var,
+                                 hipStream_t s, hipEvent_t ea, hipEvent_t eb);
 
 // Workgroup shape of a variant (threads, pencils per tile).
 template <typename R, int L>
@@ -654,6 +701,20 @@ inline void pass_shape(bool strided, int var, int* nt, int* pencils_per_tile) {
     return hipGetLastError();                                                                   \
   }
 
+#define RSFDE_LAUNCH_BATCHED_VARIANT(R, L, V)                                                   \
+  if (var == V) {                                                                               \
+    if (strided) {                                                                              \
+      using S = PassShape<R, L, true, V>;                                                       \
+      hipExtLaunchKernelGGL((rsfde_pass_batched<R, L, S::F, true>), dim3((unsigned)nblocks),    \
+                            dim3(S::NT), 0, s, ea, eb, 0, bl);                                  \
+    } else {                                                                                    \
+      using S = PassShape<R, L, false, V>;                                                      \
+      hipExtLaunchKernelGGL((rsfde_pass_batched<R, L, S::F, false>), dim3((unsigned)nblocks),   \
+                            dim3(S::NT), 0, s, ea, eb, 0, bl);                                  \
+    }                                                                                           \
+    return hipGetLastError();                                                                   \
+  }
+
 #define RSFDE_INSTANTIATE_PASS(R, L)                                                         \
   template <>                                                                                \
   hipError_t launch_pass_L<R, L>(const PassArgs& a, bool strided, int var, hipStream_t s,   \
@@ -661,5 +722,14 @@ inline void pass_shape(bool strided, int var, int* nt, int* pencils_per_tile) {
     RSFDE_LAUNCH_VARIANT(R, L, 0)                                                            \
     RSFDE_LAUNCH_VARIANT(R, L, 1)                                                            \
     RSFDE_LAUNCH_VARIANT(R, L, 2)                                                            \
+    return hipErrorInvalidValue;                                                             \
+  }                                                                                          \
+  template <>                                                                                \
+  hipError_t launch_pass_batched_L<R, L>(const BLaunch& bl, int64_t nblocks, bool strided,  \
+                                         int var, hipStream_t s, hipEvent_t ea,             \
+                                         hipEvent_t eb) {                                   \
+    RSFDE_LAUNCH_BATCHED_VARIANT(R, L, 0)                                                    \
+    RSFDE_LAUNCH_BATCHED_VARIANT(R, L, 1)                                                    \
+    RSFDE_LAUNCH_BATCHED_VARIANT(R, L, 2)                                                    \
     return hipErrorInvalidValue;                                                             \
   }

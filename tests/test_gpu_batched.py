@@ -1,0 +1,127 @@
+"""Batched form: all instances of a handle advance together (one launch per pass
+position and tile shape, one per Krylov sweep).  Each instance must come out
+exactly as when the same handle steps its instances one at a time (same
+kernels, tile shapes and reduction orders), and match the oracle."""
+import os
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_10221_amd import rsfde as R
+from rsfde_workloads import config, with_grid
+
+from gpu_helpers import empty, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+# uneven grids from both transform-length families (N+1 = 16, 24, 32, 48)
+SIZES = [(15, 31), (31, 15), (47, 23), (23, 47), (31, 31), (15, 15), (47, 47)]
+
+
+def _c4_small(k, M=3, sizes=SIZES):
+    """First k instances of the 64-instance 2-D workload on small uneven grids."""
+    insts = config("C4")
+    return [with_grid(insts[i], sizes[i % len(sizes)], M=M) for i in range(k)]
+
+
+def _solve(insts, batched, precision=R.RSFDE_FP64):
+    old = os.environ.get("RSFDE_NO_BATCH")
+    os.environ["RSFDE_NO_BATCH"] = "0" if batched else "1"
+    try:
+        S = R.Solver([R.params_from_instance(i, precision=precision) for i in insts])
+    finally:
+        if old is None:
+            del os.environ["RSFDE_NO_BATCH"]
+        else:
+            os.environ["RSFDE_NO_BATCH"] = old
+    for k, inst in enumerate(insts):
+        R.rsfde_set_fields(S.h, k, inst.e, inst.f, inst.psi)
+    us = [empty(inst.size) for inst in insts]
+    for k in range(len(insts)):
+        R.rsfde_eval_field(S.h, k, R.WHICH_PSI, 0.0, us[k])
+    status, st = R.rsfde_solve(S.h, insts[0].M, us)
+    got = [host(u) for u in us]
+    S.close()
+    return status, st, got
+
+
+def test_batched_equals_one_at_a_time_fp64():
+    insts = _c4_small(7)
+    say(f"[batched fp64] {len(insts)} instances {[i.n for i in insts]}")
+    s1, st1, g1 = _solve(insts, batched=True)
+    s0, st0, g0 = _solve(insts, batched=False)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    for k in range(len(insts)):
+        say(f"   inst {k}: iters {st1[k]['iters']} / {st0[k]['iters']}, equal {np.array_equal(g1[k], g0[k])}")
+        assert st1[k]["iters"] == st0[k]["iters"]
+        assert st1[k]["converged"] == 1
+        assert np.array_equal(g1[k], g0[k])
+
+
+def test_batched_matches_oracle():
+    insts = _c4_small(5, M=4)
+    s, st, got = _solve(insts, batched=True)
+    assert s == R.RSFDE_OK
+    for k, inst in enumerate(insts):
+        ref = O.run(inst)
+        d = rel(got[k], ref["u"])
+        say(f"   inst {k} n={inst.n}: rel diff {d:.3e}, iters {st[k]['iters']} oracle {sum(ref['iters'])}")
+        assert d <= 1e-10
+        assert abs(st[k]["iters"] - sum(ref["iters"])) <= 1
+
+
+def test_batched_uneven_convergence():
+    # different tolerances: instances leave the lockstep launches at different steps
+    insts = _c4_small(6, M=2)
+    tols = [1e-4, 1e-12, 1e-6, 1e-10, 1e-8, 1e-11]
+    insts = [replace(i, rtol=t) for i, t in zip(insts, tols)]
+    s1, st1, g1 = _solve(insts, batched=True)
+    s0, st0, g0 = _solve(insts, batched=False)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    its = [st1[k]["iters"] for k in range(len(insts))]
+    say(f"   iterations per instance {its}")
+    assert len(set(its)) > 2
+    for k in range(len(insts)):
+        assert st1[k]["iters"] == st0[k]["iters"]
+        assert np.array_equal(g1[k], g0[k])
+
+
+def test_batched_restarts():
+    # a short restart forces several cycles with instances dropping out between them
+    insts = [replace(i, restart=3, max_cycles=40) for i in _c4_small(4, M=2)]
+    s1, st1, g1 = _solve(insts, batched=True)
+    s0, st0, g0 = _solve(insts, batched=False)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    say(f"   cycles {[st1[k]['cycles'] for k in range(4)]}")
+    assert max(st1[k]["cycles"] for k in range(4)) > 2
+    for k in range(len(insts)):
+        assert np.array_equal(g1[k], g0[k])
+
+
+def test_batched_mixed_equals_one_at_a_time():
+    insts = _c4_small(5)
+    s1, st1, g1 = _solve(insts, batched=True, precision=R.RSFDE_MIXED)
+    s0, st0, g0 = _solve(insts, batched=False, precision=R.RSFDE_MIXED)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    for k, inst in enumerate(insts):
+        assert np.array_equal(g1[k], g0[k])
+        # the mixed form meets the same stopping bound ||z|| <= rtol ||z_0|| as the
+        # oracle's FP64 GMRES but along another iteration sequence, so the two
+        # solutions differ by up to about cond * rtol per step (observed 2e-10 here)
+        ref = O.run(inst)
+        assert rel(g1[k], ref["u"]) <= 5e-10
+
+
+def test_batched_full_size_workload_one_step():
+    # the 64-instance workload at its real grid sizes (N_i up to 511): one step,
+    # batched against one at a time, bit for bit
+    insts = [replace(i, M=1) for i in config("C4")]
+    say(f"[batched C4] 64 instances, {sum(i.size for i in insts)} unknowns")
+    s1, st1, g1 = _solve(insts, batched=True)
+    s0, st0, g0 = _solve(insts, batched=False)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    for k in range(64):
+        assert st1[k]["iters"] == st0[k]["iters"]
+        assert np.array_equal(g1[k], g0[k])
