@@ -7,26 +7,69 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "krylov.h"
+
+// compile-time loop (constant indices keep per-thread arrays in registers)
+template <int C, int Q = 0, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (Q < C) {
+    fn(std::integral_constant<int, Q>{});
+    static_for<C, Q + 1>(fn);
+  }
+}
 
 // threads per block for a sweep handling up to KM basis vectors
 template <int KM> struct SweepNT { static constexpr int value = KM <= 8 ? 1024 : (KM <= 16 ? 512 : 256); };
 
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+// Wavefront sums of KM values at once by recursive halving: at the step with
+// lane offset o, each lane keeps half of its values (the upper half when its
+// lane bit o is set) and adds the partner lane's copy of that half; after
+// log2(KM) steps lane l holds value l >> (6 - log2 KM), summed over the lanes
+// that agree in those top bits, and plain butterflies over the remaining low
+// bits finish the sum.  KM - 1 + 6 - log2(KM) shuffles instead of 6 KM; pairs
+// add in symmetric order, so every lane holding a value gets the same bits.
+template <int KM, int S = 0>
+__device__ __forceinline__ void wave_halve(double (&a)[KM], int lane) {
+  constexpr int Q = ilog2c(KM);
+  if constexpr (S < Q) {
+    constexpr int off = 32 >> S;
+    constexpr int half = KM >> (S + 1);
+    const bool up = (lane & off) != 0;
+    static_for<half>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const double send = up ? a[i] : a[i + half];
+      const double keep = up ? a[i + half] : a[i];
+      a[i] = keep + __shfl_xor(send, off, 64);
+    });
+    wave_halve<KM, S + 1>(a, lane);
+  }
+}
+
+template <int KM>
+__device__ __forceinline__ double wave_sums(double (&a)[KM], int lane) {
+  constexpr int Q = ilog2c(KM);
+  static_assert((1 << Q) == KM && Q <= 6, "KM must be a power of two <= 64");
+  wave_halve<KM>(a, lane);
+  double x = a[0];
+#pragma unroll
+  for (int off = 32 >> Q; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
 // Block sums of acc[0..nv) (fixed order); result in res[0..nv) (shared).
 template <int KM, int NT>
-__device__ __forceinline__ void block_sums(const double (&acc)[KM], int nv, double* res) {
+__device__ __forceinline__ void block_sums(double (&acc)[KM], int nv, double* res) {
   constexpr int NW = NT / 64;
+  constexpr int Q = ilog2c(KM);
   __shared__ double sh[NW][KM];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < KM; ++k) {
-    if (k < nv) {
-      double x = acc[k];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-      if (lane == 0) sh[wv][k] = x;
-    }
-  }
+  (void)nv;
+  const double x = wave_sums<KM>(acc, lane);
+  if ((lane & ((64 >> Q) - 1)) == 0) sh[wv][lane >> (6 - Q)] = x;
   __syncthreads();
   if ((int)threadIdx.x < nv) {
     double s = 0.0;
@@ -42,9 +85,12 @@ template <int KM, int NT>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, int nv,
                                                 double* res) {
   double acc[KM];
+  const int b = (int)threadIdx.x < nb ? (int)threadIdx.x : 0;
 #pragma unroll
-  for (int k = 0; k < KM; ++k)
-    acc[k] = ((int)threadIdx.x < nb && k < nv) ? part[k * RSFDE_PVS + threadIdx.x] : 0.0;
+  for (int k = 0; k < KM; ++k) {
+    const double v = part[(k < nv ? k : 0) * RSFDE_PVS + b];  // all loads in flight together
+    acc[k] = ((int)threadIdx.x < nb && k < nv) ? v : 0.0;
+  }
   block_sums<KM, NT>(acc, nv, res);
 }
 
@@ -104,10 +150,24 @@ k_cycle_init_fin(const double* __restrict__ partial, int nblocks, GmresState* st
   cycle_init_body(partial, nblocks, st, first, rtol, inner_rtol, mixed, m);
 }
 
+// Basis entries are loaded in chunks of up to 8 columns with no use between the
+// loads of a chunk, so a chunk costs one memory latency; columns past nv read
+// column nv - 1 (valid memory) and are discarded.
+template <int C, typename T>
+__device__ __forceinline__ void ld_cols(T (&v)[C], const T* __restrict__ V, int64_t ld, int64_t i,
+                                        int k0, int nv) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int k = k0 + c < nv ? k0 + c : nv - 1;
+    v[c] = V[k * ld + i];
+  }
+}
+
 // ---- CGS2 sweep 1: partials of Vbar^T w ---------------------------------------------------
 template <int KM>
 __device__ __forceinline__ void sweep1_body(const KryArgs& a, int bid, int nblk) {
   constexpr int NT = SweepNT<KM>::value;
+  constexpr int CH = KM < 8 ? KM : 8;
   if (a.st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
   double acc[KM];
@@ -122,16 +182,27 @@ __device__ __forceinline__ void sweep1_body(const KryArgs& a, int bid, int nblk)
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
     const double2 wi = w2[i];
 #pragma unroll
-    for (int k = 0; k < KM; ++k)
-      if (k < nv) {
-        const double2 v = V2[k * ld2 + i];
-        acc[k] += v.x * wi.x + v.y * wi.y;
+    for (int kb = 0; kb < KM; kb += CH)
+      if (kb < nv) {
+        double2 v[CH];
+        ld_cols<CH>(v, V2, ld2, i, kb, nv);
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+          if (kb + c < nv) acc[kb + c] += v[c].x * wi.x + v[c].y * wi.y;
       }
   }
   if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
-    for (int k = 0; k < KM; ++k)
-      if (k < nv) acc[k] += V[k * a.ldv + i] * w[i];
+    const double wi = w[i];
+#pragma unroll
+    for (int kb = 0; kb < KM; kb += CH)
+      if (kb < nv) {
+        double v[CH];
+        ld_cols<CH>(v, V, a.ldv, i, kb, nv);
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+          if (kb + c < nv) acc[kb + c] += v[c] * wi;
+      }
   }
   __shared__ double res[KM];
   block_sums<KM, NT>(acc, nv, res);
@@ -143,10 +214,37 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep1(const KryArgs a) 
   sweep1_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
+// w -= sum_{k < nv} cf[k] V_k at row i (columns in chunks); with KEEP the loaded
+// entries stay in vk for the dot products that follow.
+template <int KM, bool KEEP, typename T>
+__device__ __forceinline__ void sub_cols(T& wi, T (&vk)[KEEP ? KM : 1], const T* __restrict__ V,
+                                         int64_t ld, int64_t i, const double* cf, int nv) {
+  constexpr int CH = KM < 8 ? KM : 8;
+#pragma unroll
+  for (int kb = 0; kb < KM; kb += CH)
+    if (kb < nv) {
+      T v[CH];
+      ld_cols<CH>(v, V, ld, i, kb, nv);
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        if (kb + c < nv) {
+          if constexpr (sizeof(T) == 16) {
+            wi.x -= cf[kb + c] * v[c].x;
+            wi.y -= cf[kb + c] * v[c].y;
+          } else {
+            wi -= cf[kb + c] * v[c];
+          }
+          if constexpr (KEEP) vk[kb + c] = v[c];
+        }
+    }
+}
+
 // ---- CGS2 sweep 2: h = Vbar^T w / |v| ; w -= V h ; partials of Vbar^T w ------------------
 template <int KM>
 __device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk) {
   constexpr int NT = SweepNT<KM>::value;
+  constexpr int CH = KM < 8 ? KM : 8;
+  constexpr bool KEEP = KM <= 16;  // basis values kept in registers for the dots
   GmresState* st = a.st;
   if (st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
@@ -170,34 +268,39 @@ __device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk)
   const double2* __restrict__ V2 = (const double2*)V;
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
     double2 wi = w2[i];
-    constexpr int KR = KM <= 16 ? KM : 1;  // basis values kept in registers
-    double2 vk[KR];
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-      if (k < nv) {
-        const double2 v = V2[k * ld2 + i];
-        if constexpr (KM <= 16) vk[k] = v;
-        wi.x -= cf[k] * v.x;
-        wi.y -= cf[k] * v.y;
-      }
+    double2 vk[KEEP ? KM : 1];
+    sub_cols<KM, KEEP>(wi, vk, V2, ld2, i, cf, nv);
     w2[i] = wi;
 #pragma unroll
-    for (int k = 0; k < KM; ++k)
-      if (k < nv) {
-        double2 v;
-        if constexpr (KM <= 16) v = vk[k];
-        else v = V2[k * ld2 + i];
-        acc[k] += v.x * wi.x + v.y * wi.y;
+    for (int kb = 0; kb < KM; kb += CH)
+      if (kb < nv) {
+        double2 v[CH];
+        if constexpr (KEEP) {
+#pragma unroll
+          for (int c = 0; c < CH; ++c) v[c] = vk[kb + c];
+        } else {
+          ld_cols<CH>(v, V2, ld2, i, kb, nv);
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+          if (kb + c < nv) acc[kb + c] += v[c].x * wi.x + v[c].y * wi.y;
       }
   }
   if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
     double wi = w[i];
-    for (int k = 0; k < KM; ++k)
-      if (k < nv) wi -= cf[k] * V[k * a.ldv + i];
+    double vk[1];
+    sub_cols<KM, false>(wi, vk, V, a.ldv, i, cf, nv);
     w[i] = wi;
-    for (int k = 0; k < KM; ++k)
-      if (k < nv) acc[k] += V[k * a.ldv + i] * wi;
+#pragma unroll
+    for (int kb = 0; kb < KM; kb += CH)
+      if (kb < nv) {
+        double v[CH];
+        ld_cols<CH>(v, V, a.ldv, i, kb, nv);
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+          if (kb + c < nv) acc[kb + c] += v[c] * wi;
+      }
   }
   __shared__ double res[KM];
   block_sums<KM, NT>(acc, nv, res);
@@ -234,21 +337,16 @@ __device__ __forceinline__ void sweep3_body(const KryArgs& a, int bid, int nblk)
   const double2* __restrict__ V2 = (const double2*)V;
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
     double2 wi = w2[i];
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-      if (k < nv) {
-        const double2 v = V2[k * ld2 + i];
-        wi.x -= cf[k] * v.x;
-        wi.y -= cf[k] * v.y;
-      }
+    double2 vk[1];
+    sub_cols<KM, false>(wi, vk, V2, ld2, i, cf, nv);
     w2[i] = wi;
     acc[0] += wi.x * wi.x + wi.y * wi.y;
   }
   if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
     double wi = w[i];
-    for (int k = 0; k < KM; ++k)
-      if (k < nv) wi -= cf[k] * V[k * a.ldv + i];
+    double vk[1];
+    sub_cols<KM, false>(wi, vk, V, a.ldv, i, cf, nv);
     w[i] = wi;
     acc[0] += wi * wi;
   }
@@ -301,16 +399,27 @@ __device__ __forceinline__ void update_body(const double* __restrict__ V, int64_
   const double2* __restrict__ V2 = (const double2*)V;
   for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n2; i += stride) {
     double2 xi = x2[i];
-    for (int l = 0; l < k; ++l) {
-      const double2 v = V2[l * ld2 + i];
-      xi.x += cf[l] * v.x;
-      xi.y += cf[l] * v.y;
+    for (int lb = 0; lb < k; lb += 8) {
+      double2 v[8];
+      ld_cols<8>(v, V2, ld2, i, lb, k);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (lb + c < k) {
+          xi.x += cf[lb + c] * v[c].x;
+          xi.y += cf[lb + c] * v[c].y;
+        }
     }
     x2[i] = xi;
   }
   if ((n & 1) && bid == 0 && threadIdx.x == 0) {
     double xi = x[n - 1];
-    for (int l = 0; l < k; ++l) xi += cf[l] * V[l * ldv + n - 1];
+    for (int lb = 0; lb < k; lb += 8) {
+      double v[8];
+      ld_cols<8>(v, V, ldv, n - 1, lb, k);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (lb + c < k) xi += cf[lb + c] * v[c];
+    }
     x[n - 1] = xi;
   }
 }
