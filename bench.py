@@ -108,11 +108,17 @@ class Stepper:
 
     def step(self):
         R = self.R
-        for k, inst in enumerate(self.insts):
-            th = (self.m + 0.5) * inst.dt
-            R.rsfde_eval_field(self.S.h, k, R.WHICH_E, th, self.es[k])
-            if inst.f.time_dependent:
-                R.rsfde_eval_field(self.S.h, k, R.WHICH_F, th, self.fs[k])
+        th = (self.m + 0.5) * self.inst.dt
+        if len(self.insts) > 1 and all(i.dt == self.inst.dt for i in self.insts):
+            R.rsfde_eval_field_batch(self.S.h, R.WHICH_E, th, self.es)  # one launch for all
+            if any(i.f.time_dependent for i in self.insts):
+                R.rsfde_eval_field_batch(self.S.h, R.WHICH_F, th, self.fs)
+        else:
+            for k, inst in enumerate(self.insts):
+                tk = (self.m + 0.5) * inst.dt
+                R.rsfde_eval_field(self.S.h, k, R.WHICH_E, tk, self.es[k])
+                if inst.f.time_dependent:
+                    R.rsfde_eval_field(self.S.h, k, R.WHICH_F, tk, self.fs[k])
         s, st = R.rsfde_step(self.S.h, self.m * self.inst.dt, self.es, self.fs, self.us)
         self.status = max(self.status, s)
         self.iters += sum(x["iters"] for x in st)

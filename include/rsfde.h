@@ -181,6 +181,12 @@ int rsfde_set_fields(rsfde_handle h, int instance, const rsfde_field* e,
  * which = RSFDE_WHICH_E (interior), RSFDE_WHICH_F (closure grid), RSFDE_WHICH_PSI. */
 int rsfde_eval_field(rsfde_handle h, int instance, int which, double t, double* out);
 
+/* The same for every instance of the handle in one launch: out[i] (device) receives
+ * instance i's field, in the layout rsfde_eval_field uses.  Every instance needs
+ * its fields registered.  Errors: RSFDE_E_INVALID_ARG (null handle/array/entry,
+ * bad `which`), RSFDE_E_STATE (fields not registered), RSFDE_E_HIP. */
+int rsfde_eval_field_batch(rsfde_handle h, int which, double t, double* const* out);
+
 /* ---- operator entry points (single instance; device pointers; on the handle's stream) */
 
 /* out = A v = B_alpha (e .* v) + S_alpha v (eq. tls). */

@@ -132,6 +132,7 @@ struct Inst {
   int64_t n = 0, nclo = 0, ldv = 0;
   Axis ax[3];
   double *e = nullptr, *f = nullptr, *F = nullptr, *b = nullptr, *V = nullptr;
+  const double* ecur = nullptr;  // e of the current step (the caller's buffer or e)
   float* e32 = nullptr;
   void* tmp[4] = {nullptr, nullptr, nullptr, nullptr};
   GmresState* st = nullptr;
@@ -185,13 +186,32 @@ struct BGroup {
   bool fp32 = false, strided = false;
   int ninst = 0;
   int64_t nblocks = 0;
-  size_t desc_off = 0, start_off = 0;  // offsets in the batch descriptor buffer
+  const BPass* desc = nullptr;  // device copies (batch descriptor buffer)
+  const int* start = nullptr;
   int cls = 0;
   double bytes = 0;
 };
 struct BChain {
   std::vector<std::vector<BGroup>> pos;  // groups per pass position of the chain
 };
+struct KPlan {
+  int ninst = 0;
+  const KBatch* desc = nullptr;
+  const int *start_nb = nullptr, *start_nbu = nullptr;
+  int64_t nb_total = 0, nbu_total = 0;
+  double vbytes = 0;  // one FP64 vector over all instances
+  int m = 0;          // largest restart
+};
+
+struct BPlan {
+  BChain rhs, resid, oper;
+  KPlan kp;
+  const FJob* fjobs = nullptr;
+  const int* fstart = nullptr;
+  int64_t fblocks = 0;
+  int nf = 0;
+};
+
 struct RecPass {
   PassArgs a;
   bool fp32;
@@ -205,9 +225,23 @@ struct rsfde_ctx {
   bool batched = false;
   char* bdev = nullptr;          // descriptor buffer in the workspace
   char* bhost = nullptr;         // pinned staging copy
-  size_t bcap = 0, bfill = 0;
+  size_t bcap = 0;
+  struct Region {
+    size_t base = 0, cap = 0, fill = 0;
+  } rg[3];                       // 0: the step's full-set plan, 1: plans of later cycles, 2: field jobs
   GmresSummary* dsum = nullptr;  // gathered summaries (workspace) and their pinned copy
   GmresSummary* psum = nullptr;
+  int* dmask = nullptr;          // per-slot "update may add V y" flags (workspace) and pinned copy
+  int* pmask = nullptr;
+  // cached full-set plan: valid while the u, e and f pointers of a step repeat
+  BPlan full;
+  bool full_valid = false;
+  std::vector<const void*> full_key;
+  std::vector<const void*> fjob_key;   // cached batched field-evaluation jobs
+  int fjob_which = -1;
+  int64_t fjob_blocks = 0;
+  const FieldJob* fjob_dev = nullptr;
+  const int* fjob_start = nullptr;
   std::vector<RecPass>* rec = nullptr;  // chain recording instead of launching
   int rec_inst = -1;
   struct AtEntry {
@@ -457,7 +491,7 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
                      const double* sc, const double* xin, double xcoef, double* out,
                      const GmRes* gm = nullptr, const int* stop_fl = nullptr) {
   const int d = I.d;
-  const void* e = fp32 ? (const void*)I.e32 : (const void*)I.e;
+  const void* e = fp32 ? (const void*)I.e32 : (const void*)I.ecur;
   const bool prec = kind == CH_RESID || kind == CH_OPER;
   const double sgn = kind == CH_RHS ? -1.0 : 1.0;
   void* const* T = I.tmp;
@@ -721,11 +755,11 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
   if ((uintptr_t)u & 15) return RSFDE_E_INVALID_ARG;
   const rsfde_params& p = I.p;
   const bool mixed = p.precision == RSFDE_MIXED;
-  if (e_half != I.e) CK(hipMemcpyAsync(I.e, e_half, I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  I.ecur = e_half;  // read in place (no copy)
   GridDev gi = grid_dev(I, false);
   double al[3] = {I.p.alpha[0], I.p.alpha[1], I.p.alpha[2]};
   CK(compute_F(f_half, gi, al, I.F, h->stream));
-  if (mixed) CK(convert_f64_f32(I.e, I.e32, I.n, h->stream));
+  if (mixed) CK(convert_f64_f32(I.ecur, I.e32, I.n, h->stream));
   // b = (B E - S) u + dt F
   CKS(run_chain(h, I, CH_RHS, false, u, nullptr, I.F, p.dt, I.b));
   if (p.x0_mode == 1) CK(fill_f64(u, I.n, 0.0, h->stream));
@@ -800,26 +834,50 @@ static bool batchable(const rsfde_ctx* h) {
   return true;
 }
 
-// Descriptor buffer capacity for `count` instances: three chains of at most 7
-// pass positions, each with a descriptor and a block-start entry per instance
-// (64-byte aligned per group), plus the Krylov descriptors and their starts.
-static size_t batch_capacity(int count) {
+// Descriptor buffer capacity of one plan region for `count` instances: three
+// chains of at most 7 pass positions with a descriptor and a block-start entry
+// per instance (64-byte aligned per group), the Krylov descriptors with two
+// start arrays, and the source-operator jobs.
+static size_t plan_capacity(int count) {
   const size_t per_pos = (size_t)count * (sizeof(BPass) + 3 * 64 + 8) + 64;
-  return 3 * 7 * per_pos + (size_t)count * (sizeof(KBatch) + 16) + 4 * 64 + 4096;
+  return 3 * 7 * per_pos + (size_t)count * (sizeof(KBatch) + sizeof(FJob) + 32) + 8 * 64 + 4096;
+}
+static size_t fjob_capacity(int count) {
+  return (size_t)count * (sizeof(FieldJob) + 8) + 4 * 64 + 1024;
+}
+static size_t batch_capacity(int count) {
+  return 2 * plan_capacity(count) + fjob_capacity(count);
 }
 
-static size_t bappend(rsfde_ctx* h, const void* src, size_t bytes) {
-  const size_t off = (h->bfill + 63) & ~(size_t)63;
-  if (off + bytes > h->bcap) return (size_t)-1;
-  memcpy(h->bhost + off, src, bytes);
-  h->bfill = off + bytes;
-  return off;
+static void regions_init(rsfde_ctx* h) {
+  const size_t pc = plan_capacity(h->count);
+  h->rg[0] = {0, pc, 0};
+  h->rg[1] = {pc, pc, 0};
+  h->rg[2] = {2 * pc, fjob_capacity(h->count), 0};
+}
+
+// Append to region r's staging area; returns the device address of the copy
+// (valid once the region is uploaded), or nullptr when the region is full.
+static char* bappend(rsfde_ctx* h, int r, const void* src, size_t bytes) {
+  rsfde_ctx::Region& R = h->rg[r];
+  const size_t off = (R.fill + 63) & ~(size_t)63;
+  if (off + bytes > R.cap) return nullptr;
+  memcpy(h->bhost + R.base + off, src, bytes);
+  R.fill = off + bytes;
+  return h->bdev + R.base + off;
+}
+
+static hipError_t bupload(rsfde_ctx* h, int r) {
+  const rsfde_ctx::Region& R = h->rg[r];
+  if (R.fill == 0) return hipSuccess;
+  return hipMemcpyAsync(h->bdev + R.base, h->bhost + R.base, R.fill, hipMemcpyHostToDevice, h->stream);
 }
 
 // Plan of one chain over the instance set S: record each instance's passes
 // (same sequence of ops for every instance) and group them per position.
 template <typename RecFn>
-static int plan_chain(rsfde_ctx* h, const std::vector<int>& S, RecFn rec_one, bool oper, BChain& out) {
+static int plan_chain(rsfde_ctx* h, int r, const std::vector<int>& S, RecFn rec_one, bool oper,
+                      BChain& out) {
   std::vector<std::vector<RecPass>> recs(S.size());
   for (size_t s = 0; s < S.size(); ++s) {
     h->rec = &recs[s];
@@ -829,8 +887,8 @@ static int plan_chain(rsfde_ctx* h, const std::vector<int>& S, RecFn rec_one, bo
     if (st < 0) return st;
   }
   const size_t P = recs.empty() ? 0 : recs[0].size();
-  for (auto& r : recs)
-    if (r.size() != P) return RSFDE_E_STATE;
+  for (auto& rc : recs)
+    if (rc.size() != P) return RSFDE_E_STATE;
   out.pos.assign(P, {});
   for (size_t pi = 0; pi < P; ++pi) {
     std::vector<int> used(S.size(), 0);
@@ -847,33 +905,33 @@ static int plan_chain(rsfde_ctx* h, const std::vector<int>& S, RecFn rec_one, bo
       std::vector<BPass> desc;
       std::vector<int> start(1, 0);
       for (size_t s = s0; s < S.size(); ++s) {
-        const RecPass& r = recs[s][pi];
-        const Inst& I = h->inst[r.inst];
-        if (used[s] || I.ax[r.a.axis].L != g.L || r.a.var != g.var || r.fp32 != g.fp32 ||
-            (r.a.axis > 0) != g.strided || r.a.op != r0.a.op)
+        const RecPass& rp = recs[s][pi];
+        const Inst& I = h->inst[rp.inst];
+        if (used[s] || I.ax[rp.a.axis].L != g.L || rp.a.var != g.var || rp.fp32 != g.fp32 ||
+            (rp.a.axis > 0) != g.strided || rp.a.op != r0.a.op)
           continue;
         used[s] = 1;
         BPass b;
         memset(&b, 0, sizeof(b));
-        b.a = r.a;
+        b.a = rp.a;
         b.ldv = I.ldv;
         if (oper) {
-          if (r.a.in_c == (const void*)I.V) b.patch |= BP_IN_J;
-          if (r.a.out_a == (void*)(I.V + I.ldv)) b.patch |= BP_OUT_J;
-          if (r.a.use_gm) b.patch |= BP_GM;
-          if (r.a.stop_fl == &I.st->FL[0]) b.patch |= BP_STOP;
+          if (rp.a.in_c == (const void*)I.V) b.patch |= BP_IN_J;
+          if (rp.a.out_a == (void*)(I.V + I.ldv)) b.patch |= BP_OUT_J;
+          if (rp.a.use_gm) b.patch |= BP_GM;
+          if (rp.a.stop_fl == &I.st->FL[0]) b.patch |= BP_STOP;
         }
         desc.push_back(b);
-        const int64_t nb = (r.a.nlaunch + 7) / 8 * 8;  // 8-aligned: XCD order kept per instance
+        const int64_t nb = (rp.a.nlaunch + 7) / 8 * 8;  // 8-aligned: XCD order kept per instance
         if (start.back() + nb > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
         start.push_back((int)(start.back() + nb));
-        g.bytes += pass_bytes(r.a, I, r.fp32);
+        g.bytes += pass_bytes(rp.a, I, rp.fp32);
       }
       g.ninst = (int)desc.size();
       g.nblocks = start.back();
-      g.desc_off = bappend(h, desc.data(), desc.size() * sizeof(BPass));
-      g.start_off = bappend(h, start.data(), start.size() * sizeof(int));
-      if (g.desc_off == (size_t)-1 || g.start_off == (size_t)-1) return RSFDE_E_WORKSPACE;
+      g.desc = (const BPass*)bappend(h, r, desc.data(), desc.size() * sizeof(BPass));
+      g.start = (const int*)bappend(h, r, start.data(), start.size() * sizeof(int));
+      if (!g.desc || !g.start) return RSFDE_E_WORKSPACE;
       out.pos[pi].push_back(g);
     }
   }
@@ -885,8 +943,8 @@ static int launch_chain_batched(rsfde_ctx* h, const BChain& c, int j, int pend) 
     for (const BGroup& g : pos) {
       if (g.nblocks <= 0) continue;
       BLaunch bl;
-      bl.desc = (const BPass*)(h->bdev + g.desc_off);
-      bl.start = (const int*)(h->bdev + g.start_off);
+      bl.desc = g.desc;
+      bl.start = g.start;
       bl.ninst = g.ninst;
       bl.j = j;
       bl.pend = pend;
@@ -897,15 +955,8 @@ static int launch_chain_batched(rsfde_ctx* h, const BChain& c, int j, int pend) 
   return RSFDE_OK;
 }
 
-struct KPlan {
-  int ninst = 0;
-  size_t desc_off = 0, start_nb_off = 0, start_nbu_off = 0;
-  int64_t nb_total = 0, nbu_total = 0;
-  double vbytes = 0;  // one FP64 vector over all instances
-  int m = 0;          // largest restart
-};
 
-static int plan_krylov(rsfde_ctx* h, const std::vector<int>& S, double* const* u, KPlan& kp) {
+static int plan_krylov(rsfde_ctx* h, int r, const std::vector<int>& S, double* const* u, KPlan& kp) {
   std::vector<KBatch> desc;
   std::vector<int> snb(1, 0), snbu(1, 0);
   kp = KPlan();
@@ -939,46 +990,63 @@ static int plan_krylov(rsfde_ctx* h, const std::vector<int>& S, double* const* u
   kp.ninst = (int)S.size();
   kp.nb_total = snb.back();
   kp.nbu_total = snbu.back();
-  kp.desc_off = bappend(h, desc.data(), desc.size() * sizeof(KBatch));
-  kp.start_nb_off = bappend(h, snb.data(), snb.size() * sizeof(int));
-  kp.start_nbu_off = bappend(h, snbu.data(), snbu.size() * sizeof(int));
-  if (kp.desc_off == (size_t)-1 || kp.start_nb_off == (size_t)-1 || kp.start_nbu_off == (size_t)-1)
-    return RSFDE_E_WORKSPACE;
+  kp.desc = (const KBatch*)bappend(h, r, desc.data(), desc.size() * sizeof(KBatch));
+  kp.start_nb = (const int*)bappend(h, r, snb.data(), snb.size() * sizeof(int));
+  kp.start_nbu = (const int*)bappend(h, r, snbu.data(), snbu.size() * sizeof(int));
+  if (!kp.desc || !kp.start_nb || !kp.start_nbu) return RSFDE_E_WORKSPACE;
   return RSFDE_OK;
 }
 
-static KLaunch klaunch(const rsfde_ctx* h, const KPlan& kp, bool upd, int j, int pend, int first) {
+static KLaunch klaunch(const KPlan& kp, bool upd, int j, int pend, int first, const int* mask) {
   KLaunch kl;
-  kl.desc = (const KBatch*)(h->bdev + kp.desc_off);
-  kl.start = (const int*)(h->bdev + (upd ? kp.start_nbu_off : kp.start_nb_off));
+  kl.desc = kp.desc;
+  kl.start = upd ? kp.start_nbu : kp.start_nb;
   kl.ninst = kp.ninst;
   kl.j = j;
   kl.pend = pend;
   kl.first = first;
+  kl.mask = mask;
   return kl;
 }
 
-// Plans for the set S: the right-hand side chain (when rhs), the residual and
-// operator chains and the Krylov descriptors; uploaded in one copy.
-struct BPlan {
-  BChain rhs, resid, oper;
-  KPlan kp;
-};
+// Plans for the set S in region r: the source-operator jobs and the
+// right-hand side chain (when prep), the residual and operator chains and the
+// Krylov descriptors; uploaded in one copy.
 
-static int build_plans(rsfde_ctx* h, const std::vector<int>& S, double* const* u, bool rhs,
-                       bool fp32, BPlan& bp) {
-  CK(hipStreamSynchronize(h->stream));  // earlier copies out of the staging buffer are done
-  h->bfill = 0;
-  if (rhs)
-    CKS(plan_chain(h, S, [&](int i) {
+static int build_plans(rsfde_ctx* h, int r, const std::vector<int>& S, double* const* u,
+                       const double* const* f_half, bool prep, bool fp32, BPlan& bp) {
+  CK(hipStreamSynchronize(h->stream));  // earlier copies out of the staging area are done
+  h->rg[r].fill = 0;
+  bp = BPlan();
+  if (prep) {
+    std::vector<FJob> jobs;
+    std::vector<int> start(1, 0);
+    for (int i : S) {
+      Inst& I = h->inst[i];
+      FJob J;
+      memset(&J, 0, sizeof(J));
+      J.fcl = f_half[i];
+      J.g = grid_dev(I, false);
+      for (int a = 0; a < 3; ++a) J.al[a] = I.p.alpha[a];
+      J.F = I.F;
+      jobs.push_back(J);
+      start.push_back(start.back() + (int)((I.n + 255) / 256));
+    }
+    bp.nf = (int)jobs.size();
+    bp.fblocks = start.back();
+    bp.fjobs = (const FJob*)bappend(h, r, jobs.data(), jobs.size() * sizeof(FJob));
+    bp.fstart = (const int*)bappend(h, r, start.data(), start.size() * sizeof(int));
+    if (!bp.fjobs || !bp.fstart) return RSFDE_E_WORKSPACE;
+    CKS(plan_chain(h, r, S, [&](int i) {
       Inst& I = h->inst[i];
       return run_chain(h, I, CH_RHS, false, u[i], nullptr, I.F, I.p.dt, I.b);
     }, false, bp.rhs));
-  CKS(plan_chain(h, S, [&](int i) {
+  }
+  CKS(plan_chain(h, r, S, [&](int i) {
     Inst& I = h->inst[i];
     return run_chain(h, I, CH_RESID, false, u[i], nullptr, I.b, 1.0, I.V);
   }, false, bp.resid));
-  CKS(plan_chain(h, S, [&](int i) {
+  CKS(plan_chain(h, r, S, [&](int i) {
     Inst& I = h->inst[i];
     GmRes g;
     g.st = I.st;
@@ -989,13 +1057,13 @@ static int build_plans(rsfde_ctx* h, const std::vector<int>& S, double* const* u
     g.m = I.p.restart;
     return run_chain(h, I, CH_OPER, fp32, I.V, nullptr, nullptr, 0.0, I.V + I.ldv, &g, &I.st->FL[0]);
   }, true, bp.oper));
-  CKS(plan_krylov(h, S, u, bp.kp));
-  CK(hipMemcpyAsync(h->bdev, h->bhost, h->bfill, hipMemcpyHostToDevice, h->stream));
+  CKS(plan_krylov(h, r, S, u, bp.kp));
+  CK(bupload(h, r));
   return RSFDE_OK;
 }
 
 static int read_summaries(rsfde_ctx* h, const KPlan& kp) {
-  CK(kry_gather_summaries((const KBatch*)(h->bdev + kp.desc_off), kp.ninst, h->dsum, h->stream));
+  CK(kry_gather_summaries(kp.desc, kp.ninst, h->dsum, h->stream));
   CK(hipMemcpyAsync(h->psum, h->dsum, kp.ninst * sizeof(GmresSummary), hipMemcpyDeviceToHost,
                     h->stream));
   CK(hipStreamSynchronize(h->stream));
@@ -1003,12 +1071,20 @@ static int read_summaries(rsfde_ctx* h, const KPlan& kp) {
   return RSFDE_OK;
 }
 
-// One lockstep GMRES cycle over the set S (cycle start already launched); on
-// return fin[i] holds each instance's final summary of the cycle.
-static int run_cycle_batched(rsfde_ctx* h, std::vector<int> S, double* const* u, bool fp32,
-                             BPlan& bp, std::vector<GmresSummary>& fin) {
+// One lockstep GMRES cycle over the plan's instance set (cycle start already
+// launched); on return fin[i] holds each instance's final summary of the cycle.
+// An instance whose cycle ended in an earlier chunk stays in the launches (its
+// kernels exit on its status words) but its update is masked off, so V y is
+// added exactly once.
+static int run_cycle_batched(rsfde_ctx* h, const std::vector<int>& S, bool fp32, BPlan& bp,
+                             std::vector<GmresSummary>& fin) {
+  (void)fp32;
   int kprev = 1;
   for (int i : S) kprev = std::max(kprev, h->inst[i].k_prev);
+  const int ns = (int)S.size();
+  for (int s = 0; s < ns; ++s) h->pmask[s] = 1;
+  CK(hipMemcpyAsync(h->dmask, h->pmask, ns * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  std::vector<char> done(ns, 0);
   int j = 0, pending = -1;
   int chunk = std::max(1, std::min(bp.kp.m, kprev));
   while (true) {
@@ -1017,34 +1093,38 @@ static int run_cycle_batched(rsfde_ctx* h, std::vector<int> S, double* const* u,
     for (int jj = j; jj < jend; ++jj) {
       CKS(launch_chain_batched(h, bp.oper, jj, jj == j ? pending : jj - 1));
       for (int w = 1; w <= 3; ++w) {
-        const KLaunch kl = klaunch(h, bp.kp, false, jj, -1, 0);
+        const KLaunch kl = klaunch(bp.kp, false, jj, -1, 0, nullptr);
         const int cls = w == 1 ? RSFDE_K_DOTS : (w == 2 ? RSFDE_K_ORTH_DOTS : RSFDE_K_ORTH_NORM);
         CKS(timed_launch(h, cls, bp.kp.vbytes * (jj + 2 + (w > 1 ? 1 : 0)), [&](hipEvent_t ea, hipEvent_t eb) {
           return kry_sweep_batched(w, kl, bp.kp.nb_total, h->stream, ea, eb);
         }));
       }
     }
-    const KLaunch ku = klaunch(h, bp.kp, true, jend - 1, jend - 1, 0);
+    const KLaunch ku = klaunch(bp.kp, true, jend - 1, jend - 1, 0, h->dmask);
     CKS(timed_launch(h, RSFDE_K_UPDATE, 0.0, [&](hipEvent_t ea, hipEvent_t eb) {
       return kry_update_batched(ku, bp.kp.nbu_total, h->stream, ea, eb);
     }));
     CKS(read_summaries(h, bp.kp));
-    std::vector<int> run;
-    for (size_t s = 0; s < S.size(); ++s) {
+    int running = 0;
+    bool newly = false;
+    for (int s = 0; s < ns; ++s) {
+      if (done[s]) continue;
       const GmresSummary& G = h->psum[s];
-      if (G.flag == GM_RUNNING) run.push_back(S[s]);
-      else fin[S[s]] = G;
+      if (G.flag == GM_RUNNING) {
+        ++running;
+      } else {
+        fin[S[s]] = G;
+        done[s] = 1;
+        h->pmask[s] = 0;
+        newly = true;
+      }
     }
-    if (run.empty()) return RSFDE_OK;
+    if (running == 0) return RSFDE_OK;
     j = jend;
     pending = -1;
     chunk = 1;
     if (j >= bp.kp.m) return RSFDE_OK;  // cannot happen: the last step of a cycle never runs on
-    if (run.size() < S.size()) {
-      // finished instances leave the launches (their solution update is done)
-      S = run;
-      CKS(build_plans(h, S, u, false, fp32, bp));
-    }
+    if (newly) CK(hipMemcpyAsync(h->dmask, h->pmask, ns * sizeof(int), hipMemcpyHostToDevice, h->stream));
   }
 }
 
@@ -1056,21 +1136,28 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
     Inst& I = h->inst[i];
     if (!I.ebar_set) return RSFDE_E_STATE;
     if ((uintptr_t)u[i] & 15) return RSFDE_E_INVALID_ARG;
-  }
-  for (int i = 0; i < C; ++i) {
-    Inst& I = h->inst[i];
-    if (e_half[i] != I.e)
-      CK(hipMemcpyAsync(I.e, e_half[i], I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-    GridDev gi = grid_dev(I, false);
-    double al[3] = {I.p.alpha[0], I.p.alpha[1], I.p.alpha[2]};
-    CK(compute_F(f_half[i], gi, al, I.F, h->stream));
-    if (mixed) CK(convert_f64_f32(I.e, I.e32, I.n, h->stream));
+    I.ecur = e_half[i];  // read in place
   }
   std::vector<int> act(C);
   for (int i = 0; i < C; ++i) act[i] = i;
-  BPlan bp;
-  CKS(build_plans(h, act, u, true, mixed, bp));
-  CKS(launch_chain_batched(h, bp.rhs, 0, -1));
+  // the full-set plan is reused while the step's buffers repeat
+  std::vector<const void*> key(3 * C);
+  for (int i = 0; i < C; ++i) {
+    key[3 * i] = u[i];
+    key[3 * i + 1] = e_half[i];
+    key[3 * i + 2] = f_half[i];
+  }
+  if (!h->full_valid || key != h->full_key) {
+    h->full_valid = false;
+    CKS(build_plans(h, 0, act, u, f_half, true, mixed, h->full));
+    h->full_key = key;
+    h->full_valid = true;
+  }
+  BPlan& bp0 = h->full;
+  CK(compute_F_batched(bp0.fjobs, bp0.fstart, bp0.nf, bp0.fblocks, h->stream));
+  if (mixed)
+    for (int i = 0; i < C; ++i) CK(convert_f64_f32(h->inst[i].ecur, h->inst[i].e32, h->inst[i].n, h->stream));
+  CKS(launch_chain_batched(h, bp0.rhs, 0, -1));
   for (int i = 0; i < C; ++i)
     if (h->inst[i].p.x0_mode == 1) CK(fill_f64(u[i], h->inst[i].n, 0.0, h->stream));
   std::vector<int> status(C, RSFDE_W_NOT_CONVERGED);
@@ -1078,12 +1165,17 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
   memset(st.data(), 0, sizeof(rsfde_stats) * C);
   std::vector<GmresSummary> last(C);
   memset(last.data(), 0, sizeof(GmresSummary) * C);
+  BPlan sub;
   for (int cyc = 0; !act.empty(); ++cyc) {
-    if (cyc > 0) CKS(build_plans(h, act, u, false, mixed, bp));
-    CKS(launch_chain_batched(h, bp.resid, 0, -1));
+    BPlan* bp = &bp0;
+    if ((int)act.size() < C) {
+      CKS(build_plans(h, 1, act, u, f_half, false, mixed, sub));
+      bp = &sub;
+    }
+    CKS(launch_chain_batched(h, bp->resid, 0, -1));
     {
-      const KLaunch kl = klaunch(h, bp.kp, false, 0, -1, cyc == 0 ? 1 : 0);
-      CK(kry_norm_batched(kl, bp.kp.nb_total, h->stream));
+      const KLaunch kl = klaunch(bp->kp, false, 0, -1, cyc == 0 ? 1 : 0, nullptr);
+      CK(kry_norm_batched(kl, bp->kp.nb_total, h->stream));
       CK(kry_cycle_fin_batched(kl, h->stream));
     }
     std::vector<int> go;  // instances that run a cycle now
@@ -1095,7 +1187,7 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
         if (cyc == max_outer) any_final = true;
       }
       if (any_final) {
-        CKS(read_summaries(h, bp.kp));
+        CKS(read_summaries(h, bp->kp));
         for (size_t s = 0; s < act.size(); ++s) {
           const int i = act[s];
           const int max_outer = h->inst[i].p.max_outer > 0 ? h->inst[i].p.max_outer : 30;
@@ -1106,7 +1198,10 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
             go.push_back(i);
           }
         }
-        if (go.size() < act.size() && !go.empty()) CKS(build_plans(h, go, u, false, mixed, bp));
+        if (!go.empty() && go.size() < act.size()) {
+          CKS(build_plans(h, 1, go, u, f_half, false, mixed, sub));
+          bp = &sub;
+        }
       } else {
         go = act;
       }
@@ -1116,7 +1211,7 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
     if (go.empty()) break;
     std::vector<GmresSummary> fin(C);
     memset(fin.data(), 0, sizeof(GmresSummary) * C);
-    CKS(run_cycle_batched(h, go, u, mixed, bp, fin));
+    CKS(run_cycle_batched(h, go, mixed, *bp, fin));
     std::vector<int> next;
     for (int i : go) {
       Inst& I = h->inst[i];
@@ -1279,6 +1374,7 @@ int rsfde_workspace_size(const rsfde_params* p, int count, size_t* bytes) {
   if (count > 1) {
     (void)B.take<char>(batch_capacity(count));
     (void)B.take<GmresSummary>((size_t)count);
+    (void)B.take<int>((size_t)count);
   }
   *bytes = (B.off + 255) & ~(size_t)255;
   return RSFDE_OK;
@@ -1304,11 +1400,13 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
     he = hipHostMalloc((void**)&h->bhost, h->bcap, hipHostMallocDefault);
     if (he == hipSuccess)
       he = hipHostMalloc((void**)&h->psum, (size_t)count * sizeof(GmresSummary), hipHostMallocDefault);
+    if (he == hipSuccess) he = hipHostMalloc((void**)&h->pmask, (size_t)count * sizeof(int), hipHostMallocDefault);
   }
   if (he != hipSuccess) {
     g_last_hip = he;
     if (h->pinned) (void)hipHostFree(h->pinned);
     if (h->bhost) (void)hipHostFree(h->bhost);
+    if (h->psum) (void)hipHostFree(h->psum);
     delete h;
     return RSFDE_E_HIP;
   }
@@ -1355,6 +1453,8 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
   if (status == RSFDE_OK && count > 1) {
     h->bdev = B.take<char>(h->bcap);
     h->dsum = B.take<GmresSummary>((size_t)count);
+    h->dmask = B.take<int>((size_t)count);
+    regions_init(h);
     h->batched = batchable(h);
   }
   if (status == RSFDE_OK) {
@@ -1369,6 +1469,7 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
     (void)hipHostFree(h->pinned);
     if (h->bhost) (void)hipHostFree(h->bhost);
     if (h->psum) (void)hipHostFree(h->psum);
+    if (h->pmask) (void)hipHostFree(h->pmask);
     delete h;
     return status;
   }
@@ -1520,6 +1621,7 @@ int rsfde_destroy(rsfde_handle h) {
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->bhost) (void)hipHostFree(h->bhost);
   if (h->psum) (void)hipHostFree(h->psum);
+  if (h->pmask) (void)hipHostFree(h->pmask);
   delete h;
   return RSFDE_OK;
 }
@@ -1550,6 +1652,7 @@ const char* rsfde_strerror(int status) {
 
 int rsfde_set_fields(rsfde_handle h, int instance, const rsfde_field* e, const rsfde_field* f,
                      const rsfde_field* psi) {
+  if (h) h->fjob_key.clear();  // batched field jobs are rebuilt
   if (!h || instance < 0 || instance >= h->count || !e || !f || !psi) return RSFDE_E_INVALID_ARG;
   Inst& I = h->inst[instance];
   const int d = I.d;
@@ -1639,10 +1742,53 @@ int rsfde_eval_field(rsfde_handle h, int instance, int which, double t, double* 
   return eval_field(h, I, which, t, out);
 }
 
+int rsfde_eval_field_batch(rsfde_handle h, int which, double t, double* const* out) {
+  if (!h || !out) return RSFDE_E_INVALID_ARG;
+  if (which < RSFDE_WHICH_E || which > RSFDE_WHICH_PSI) return RSFDE_E_INVALID_ARG;
+  for (int i = 0; i < h->count; ++i) {
+    if (!out[i]) return RSFDE_E_INVALID_ARG;
+    if (!h->inst[i].fe.set) return RSFDE_E_STATE;
+  }
+  if (h->count == 1 || !h->bdev) {
+    for (int i = 0; i < h->count; ++i) CKS(eval_field(h, h->inst[i], which, t, out[i]));
+    return RSFDE_OK;
+  }
+  std::vector<const void*> key(out, out + h->count);
+  if (key != h->fjob_key || which != h->fjob_which) {
+    CK(hipStreamSynchronize(h->stream));  // the staging area is free
+    h->fjob_key.clear();
+    h->rg[2].fill = 0;
+    std::vector<FieldJob> jobs;
+    std::vector<int> start(1, 0);
+    for (int i = 0; i < h->count; ++i) {
+      Inst& I = h->inst[i];
+      FieldJob J;
+      memset(&J, 0, sizeof(J));
+      J.e = field_dev(I, I.fe, true);
+      J.f = field_dev(I, which == RSFDE_WHICH_PSI ? I.fpsi : I.ff, false);
+      if (which == RSFDE_WHICH_PSI) J.f.a = (int)llround(I.fpsi.spec.c[1]);
+      J.g = grid_dev(I, which == RSFDE_WHICH_F);
+      J.which = which;
+      J.out = out[i];
+      jobs.push_back(J);
+      start.push_back(start.back() + (int)((J.g.size + 255) / 256));
+    }
+    h->fjob_dev = (const FieldJob*)bappend(h, 2, jobs.data(), jobs.size() * sizeof(FieldJob));
+    h->fjob_start = (const int*)bappend(h, 2, start.data(), start.size() * sizeof(int));
+    if (!h->fjob_dev || !h->fjob_start) return RSFDE_E_WORKSPACE;
+    h->fjob_blocks = start.back();
+    CK(bupload(h, 2));
+    h->fjob_key = key;
+    h->fjob_which = which;
+  }
+  CK(fields_eval_batched(h->fjob_dev, h->fjob_start, h->count, h->fjob_blocks, t, h->stream));
+  return RSFDE_OK;
+}
+
 int rsfde_apply_A(rsfde_handle h, int instance, const double* e, const double* v, double* out) {
   if (!h || instance < 0 || instance >= h->count || !e || !v || !out) return RSFDE_E_INVALID_ARG;
   Inst& I = h->inst[instance];
-  if (e != I.e) CK(hipMemcpyAsync(I.e, e, I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  I.ecur = e;
   return run_chain(h, I, CH_APPLY_A, false, v, nullptr, nullptr, 0.0, out);
 }
 
@@ -1665,7 +1811,7 @@ int rsfde_rhs(rsfde_handle h, int instance, const double* e, const double* F, co
               double* out) {
   if (!h || instance < 0 || instance >= h->count || !e || !F || !u || !out) return RSFDE_E_INVALID_ARG;
   Inst& I = h->inst[instance];
-  if (e != I.e) CK(hipMemcpyAsync(I.e, e, I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  I.ecur = e;
   return run_chain(h, I, CH_RHS, false, u, nullptr, F, I.p.dt, out);
 }
 

@@ -28,8 +28,28 @@ struct GridDev {
   int64_t size;
 };
 
+// one instance's field evaluation and its source operator, for batched launches
+struct FieldJob {
+  FieldDev e, f;
+  GridDev g;
+  int which, pad;
+  double* out;
+};
+struct FJob {
+  const double* fcl;
+  GridDev g;
+  double al[3];
+  double* F;
+};
+
 hipError_t fields_eval(const FieldDev& e, const FieldDev& f, int which, const GridDev& g, double t,
                        double* out, hipStream_t s);
+// jobs and start in device memory; block b of the launch works on the job whose
+// block range start[s] .. start[s+1) holds b (blocks of 256 threads)
+hipError_t fields_eval_batched(const FieldJob* jobs, const int* start, int n, int64_t nblocks,
+                               double t, hipStream_t s);
+hipError_t compute_F_batched(const FJob* jobs, const int* start, int n, int64_t nblocks,
+                             hipStream_t s);
 hipError_t fields_sintab(int K, int Ncl, double lo, double h, double* tab, hipStream_t s);
 hipError_t compute_F(const double* fcl, const GridDev& interior, const double* alpha, double* F,
                      hipStream_t s);

@@ -79,10 +79,9 @@ __device__ __forceinline__ double riesz_poly(const double* mc, double alpha, int
   return mc[26] * acc;
 }
 
-__global__ void __launch_bounds__(256)
-k_fields_eval(const FieldDev E, const FieldDev F, int which, const GridDev g, double t,
-              double* __restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fields_eval_at(const FieldDev& E, const FieldDev& F, int which,
+                                               const GridDev& g, double t, double* __restrict__ out,
+                                               int64_t idx) {
   if (idx >= g.size) return;
   const int d = g.d;
   int jc[3] = {0, 0, 0};
@@ -137,6 +136,28 @@ k_fields_eval(const FieldDev E, const FieldDev F, int which, const GridDev g, do
   out[idx] = v;
 }
 
+__global__ void __launch_bounds__(256)
+k_fields_eval(const FieldDev E, const FieldDev F, int which, const GridDev g, double t,
+              double* __restrict__ out) {
+  fields_eval_at(E, F, which, g, t, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// one launch for many instances: job[s] covers blocks start[s] .. start[s+1)
+__global__ void __launch_bounds__(256)
+k_fields_eval_b(const FieldJob* __restrict__ jobs, const int* __restrict__ start, int n, double t) {
+  const int slot = batch_slot(start, n, blockIdx.x);
+  const FieldJob& J = jobs[slot];
+  fields_eval_at(J.e, J.f, J.which, J.g, t, J.out,
+                 (int64_t)((int)blockIdx.x - start[slot]) * blockDim.x + threadIdx.x);
+}
+
+hipError_t fields_eval_batched(const FieldJob* jobs, const int* start, int n, int64_t nblocks,
+                               double t, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fields_eval_b, dim3((unsigned)nblocks), dim3(256), 0, s, jobs, start, n, t);
+  return hipGetLastError();
+}
+
 hipError_t fields_eval(const FieldDev& e, const FieldDev& f, int which, const GridDev& g, double t,
                        double* out, hipStream_t s) {
   if (g.size == 0) return hipSuccess;
@@ -160,10 +181,9 @@ hipError_t fields_sintab(int K, int Ncl, double lo, double h, double* tab, hipSt
 // F_J = sum over the 3^d neighbours of prod_i w_i(a_i) f_{J+a} on the closure
 // grid, w(0) = 1 - alpha_i/12, w(+-1) = alpha_i/24 (every interior index lies
 // inside the stencil's support, so H acts as the stencil on each axis).
-__global__ void __launch_bounds__(256)
-k_compute_F(const double* __restrict__ fcl, const GridDev g, double a0, double a1, double a2,
-            double* __restrict__ F) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void compute_F_at(const double* __restrict__ fcl, const GridDev& g,
+                                             double a0, double a1, double a2,
+                                             double* __restrict__ F, int64_t idx) {
   if (idx >= g.size) return;
   const int d = g.d;
   const double al[3] = {a0, a1, a2};
@@ -203,6 +223,27 @@ k_compute_F(const double* __restrict__ fcl, const GridDev g, double a0, double a
     }
   }
   F[idx] = acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_compute_F(const double* __restrict__ fcl, const GridDev g, double a0, double a1, double a2,
+            double* __restrict__ F) {
+  compute_F_at(fcl, g, a0, a1, a2, F, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256)
+k_compute_F_b(const FJob* __restrict__ jobs, const int* __restrict__ start, int n) {
+  const int slot = batch_slot(start, n, blockIdx.x);
+  const FJob& J = jobs[slot];
+  compute_F_at(J.fcl, J.g, J.al[0], J.al[1], J.al[2], J.F,
+               (int64_t)((int)blockIdx.x - start[slot]) * blockDim.x + threadIdx.x);
+}
+
+hipError_t compute_F_batched(const FJob* jobs, const int* start, int n, int64_t nblocks,
+                             hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compute_F_b, dim3((unsigned)nblocks), dim3(256), 0, s, jobs, start, n);
+  return hipGetLastError();
 }
 
 hipError_t compute_F(const double* fcl, const GridDev& g, const double* alpha, double* F,

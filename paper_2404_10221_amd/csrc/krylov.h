@@ -240,18 +240,6 @@ __device__ __forceinline__ void gm_prologue(const GmRes& g, GmOut* o, GmCol* col
   gm_resolve(g, in, o, col, writer);
 }
 
-// Slot of block `bid`: the number of slots s >= 1 with start[s] <= bid (one
-// ballot per 64 slots, identical in every wavefront).
-__device__ __forceinline__ int batch_slot(const int* __restrict__ start, int n, int bid) {
-  int slot = 0;
-  const int lane = threadIdx.x & 63;
-  for (int base = 0; base < n; base += 64) {
-    const int i = base + lane;
-    const bool le = i < n && start[i + 1] <= bid;
-    slot += __popcll(__ballot(le));
-  }
-  return __builtin_amdgcn_readfirstlane(slot);
-}
 
 struct KryArgs {
   const double* V;    // basis, column k at V + k*ldv
@@ -289,6 +277,7 @@ struct KBatch {
 struct KLaunch {
   const KBatch* desc;  // slot order
   const int* start;    // block prefix sums of the launch (per-instance block counts)
+  const int* mask;     // update: slot s adds V y only when mask[s] != 0 (NULL: all)
   int ninst;
   int j, pend, first;
 };

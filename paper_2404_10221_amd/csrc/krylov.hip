@@ -498,6 +498,7 @@ __global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep_b(const KLaunch kl
 
 __global__ void __launch_bounds__(256) k_update_b(const KLaunch kl) {
   const int slot = batch_slot(kl.start, kl.ninst, blockIdx.x);
+  if (kl.mask && kl.mask[slot] == 0) return;  // this instance's update was added earlier
   const KBatch& d = kl.desc[slot];
   GmRes g;
   g.st = d.k.st;

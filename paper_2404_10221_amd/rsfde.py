@@ -35,7 +35,8 @@ WHICH_E, WHICH_F, WHICH_PSI = 0, 1, 2
 
 EXPORTED = (
     "rsfde_workspace_size", "rsfde_setup", "rsfde_set_ebar", "rsfde_step", "rsfde_solve",
-    "rsfde_destroy", "rsfde_strerror", "rsfde_set_fields", "rsfde_eval_field", "rsfde_apply_A",
+    "rsfde_destroy", "rsfde_strerror", "rsfde_set_fields", "rsfde_eval_field",
+    "rsfde_eval_field_batch", "rsfde_apply_A",
     "rsfde_apply_prec", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
     "rsfde_get_timing", "rsfde_prescan_ebar",
 )
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_strerror.restype = C.c_char_p
     lib.rsfde_set_fields.argtypes = [P, I, C.POINTER(rsfde_field), C.POINTER(rsfde_field), C.POINTER(rsfde_field)]
     lib.rsfde_eval_field.argtypes = [P, I, I, D, P]
+    lib.rsfde_eval_field_batch.argtypes = [P, I, D, C.POINTER(P)]
     lib.rsfde_apply_A.argtypes = [P, I, P, P, P]
     lib.rsfde_apply_prec.argtypes = [P, I, P, P]
     lib.rsfde_compute_F.argtypes = [P, I, P, P]
@@ -239,6 +241,10 @@ def rsfde_set_fields(h, instance: int, e_spec, f_spec, psi_spec) -> None:
 
 def rsfde_eval_field(h, instance: int, which: int, t: float, out) -> None:
     _check(load_library().rsfde_eval_field(h, instance, which, t, _ptr(out)), "rsfde_eval_field")
+
+
+def rsfde_eval_field_batch(h, which: int, t: float, outs: Sequence) -> None:
+    _check(load_library().rsfde_eval_field_batch(h, which, t, _ptr_array(outs)), "rsfde_eval_field_batch")
 
 
 def rsfde_apply_A(h, instance: int, e, v, out) -> None:

@@ -125,3 +125,61 @@ def test_batched_full_size_workload_one_step():
     for k in range(64):
         assert st1[k]["iters"] == st0[k]["iters"]
         assert np.array_equal(g1[k], g0[k])
+
+
+def test_eval_field_batch_matches_per_instance():
+    insts = _c4_small(5)
+    S = R.Solver([R.params_from_instance(i) for i in insts])
+    for k, inst in enumerate(insts):
+        R.rsfde_set_fields(S.h, k, inst.e, inst.f, inst.psi)
+    for which, closure in ((R.WHICH_E, False), (R.WHICH_F, True), (R.WHICH_PSI, False)):
+        sizes = [int(np.prod([v + 2 if closure else v for v in i.n])) for i in insts]
+        a = [empty(n) for n in sizes]
+        b = [empty(n) for n in sizes]
+        for t in (0.0, 0.3125):
+            R.rsfde_eval_field_batch(S.h, which, t, a)
+            for k in range(len(insts)):
+                R.rsfde_eval_field(S.h, k, which, t, b[k])
+            for k in range(len(insts)):
+                assert np.array_equal(host(a[k]), host(b[k]))
+    S.close()
+
+
+def test_batched_step_with_changing_buffers():
+    # new u / e / f buffers between steps: the batched plan is rebuilt, results unchanged
+    import torch
+    insts = _c4_small(4, M=3)
+
+    def run(batched):
+        old = os.environ.get("RSFDE_NO_BATCH")
+        os.environ["RSFDE_NO_BATCH"] = "0" if batched else "1"
+        try:
+            S = R.Solver([R.params_from_instance(i) for i in insts])
+        finally:
+            if old is None:
+                del os.environ["RSFDE_NO_BATCH"]
+            else:
+                os.environ["RSFDE_NO_BATCH"] = old
+        for k, inst in enumerate(insts):
+            R.rsfde_set_fields(S.h, k, inst.e, inst.f, inst.psi)
+            R.rsfde_prescan_ebar(S.h, k, inst.M)
+        us = [empty(i.size) for i in insts]
+        for k in range(len(insts)):
+            R.rsfde_eval_field(S.h, k, R.WHICH_PSI, 0.0, us[k])
+        for m in range(insts[0].M):
+            th = (m + 0.5) * insts[0].dt
+            es = [empty(i.size) for i in insts]
+            fs = [empty(int(np.prod([v + 2 for v in i.n]))) for i in insts]
+            R.rsfde_eval_field_batch(S.h, R.WHICH_E, th, es)
+            R.rsfde_eval_field_batch(S.h, R.WHICH_F, th, fs)
+            st, _ = R.rsfde_step(S.h, m * insts[0].dt, es, fs, us)
+            assert st == R.RSFDE_OK
+            us = [u.clone() for u in us]  # the next step works on fresh buffers
+        got = [host(u) for u in us]
+        S.close()
+        return got
+
+    g1 = run(True)
+    g0 = run(False)
+    for k in range(len(insts)):
+        assert np.array_equal(g1[k], g0[k])
