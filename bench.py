@@ -101,22 +101,26 @@ class Stepper:
             self.fs.append(torch.empty(ncl, dtype=torch.float64, device="cuda"))
             R.rsfde_eval_field(self.S.h, k, R.WHICH_PSI, 0.0, self.us[k])
             R.rsfde_eval_field(self.S.h, k, R.WHICH_F, 0.5 * inst.dt, self.fs[k])
+            R.rsfde_eval_field(self.S.h, k, R.WHICH_E, 0.5 * inst.dt, self.es[k])
         self.u = self.us[0]
         self.m = 0
         self.iters = 0
         self.status = 0
 
     def step(self):
+        # e and f at t_{m+1/2}; a field that does not depend on t keeps its first evaluation
         R = self.R
         th = (self.m + 0.5) * self.inst.dt
         if len(self.insts) > 1 and all(i.dt == self.inst.dt for i in self.insts):
-            R.rsfde_eval_field_batch(self.S.h, R.WHICH_E, th, self.es)  # one launch for all
+            if any(i.e.time_dependent for i in self.insts):
+                R.rsfde_eval_field_batch(self.S.h, R.WHICH_E, th, self.es)  # one launch for all
             if any(i.f.time_dependent for i in self.insts):
                 R.rsfde_eval_field_batch(self.S.h, R.WHICH_F, th, self.fs)
         else:
             for k, inst in enumerate(self.insts):
                 tk = (self.m + 0.5) * inst.dt
-                R.rsfde_eval_field(self.S.h, k, R.WHICH_E, tk, self.es[k])
+                if inst.e.time_dependent:
+                    R.rsfde_eval_field(self.S.h, k, R.WHICH_E, tk, self.es[k])
                 if inst.f.time_dependent:
                     R.rsfde_eval_field(self.S.h, k, R.WHICH_F, tk, self.fs[k])
         s, st = R.rsfde_step(self.S.h, self.m * self.inst.dt, self.es, self.fs, self.us)
