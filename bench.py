@@ -82,13 +82,15 @@ class Stepper:
     """Owns a handle on one or more instances (several: batched launches) and steps
     them together with device-evaluated fields."""
 
-    def __init__(self, insts, **over):
+    def __init__(self, insts, graphs=False, **over):
         import torch
         from paper_2404_10221_amd import rsfde as R
         self.R = R
         self.insts = list(insts) if isinstance(insts, (list, tuple)) else [insts]
         self.inst = self.insts[0]
         self.S = R.Solver([R.params_from_instance(i, **over) for i in self.insts])
+        if graphs:
+            R.rsfde_set_graph(self.S.h, True)
         self.us, self.es, self.fs = [], [], []
         for k, inst in enumerate(self.insts):
             R.rsfde_set_fields(self.S.h, k, inst.e, inst.f, inst.psi)
@@ -208,6 +210,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="skip the run with graph replay of the Arnoldi steps")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--cpu-instances", type=int, default=4,
                     help="instances of a many-instance workload the oracle baseline samples")
@@ -316,6 +320,24 @@ def main():
                         "gmres_iters_per_step": (gm.iters - it0) / K,
                         "rel_diff_vs_fp64_gpu": diff, "status": gm.status}
         gm.close()
+
+    # ---- FP64 form with graph replay of the Arnoldi steps (no kernel timing)
+    if not args.no_graphs:
+        gg = Stepper(insts, graphs=True)
+        for _ in range(W):
+            gg.step()
+        it0 = gg.iters
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            gg.step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        same = all(bool(torch.equal(a, b)) for a, b in zip(gg.us, u64))
+        out["graph_replay"] = {"value": K / el, "unit": "time-steps/s", "ms_per_step": 1e3 * el / K,
+                               "gmres_iters_per_step": (gg.iters - it0) / K,
+                               "bitwise_equal_to_direct": same, "status": gg.status}
+        gg.close()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = (cpu_baseline(inst, args.cpu_steps) if len(insts) == 1

@@ -215,6 +215,17 @@ int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* 
  * Time-independent fields are sampled once. */
 int rsfde_prescan_ebar(rsfde_handle h, int instance, int M);
 
+/* Graph replay (enable = 1) or direct launches (0, the default) for the Arnoldi
+ * steps.  With replay on, each step's launch sequence (operator chain and the
+ * three CGS2 sweeps) is captured once per (step index, pending resolve) on a
+ * private stream and replayed as one graph on the handle's stream; results are
+ * bit-identical to direct launches.  Steps are launched directly while a kernel
+ * class is being timed (rsfde_set_timing), and in batched cycles that run on a
+ * partial instance set.  Captured graphs follow the e buffer and the batched
+ * plan; they are released by rsfde_set_graph(h, 0) and rsfde_destroy.
+ * Errors: RSFDE_E_INVALID_ARG, RSFDE_E_HIP. */
+int rsfde_set_graph(rsfde_handle h, int enable);
+
 /* Kernel classes for HIP-event timing (bit i of the mask enables class i). */
 #define RSFDE_K_MV_FIRST    0  /* first-axis operator pass */
 #define RSFDE_K_MV_MID      1  /* middle-axis operator pass (d = 3) */

@@ -152,6 +152,8 @@ struct Inst {
   double* fsin_e[3] = {nullptr, nullptr, nullptr};
   double* fsin_f[3] = {nullptr, nullptr, nullptr};
   int k_prev = 4;
+  std::vector<hipGraphExec_t> gexec;  // captured Arnoldi steps: [2 j + (resolve pending)]
+  const void* g_e = nullptr;           // e the captured steps read
   int var[3][2][2] = {};  // tile variant per axis, precision (FP64, FP32) and pass class
                           // (0: operator passes, 1: transform passes)
 };
@@ -221,6 +223,11 @@ struct RecPass {
 struct rsfde_ctx {
   int count = 0;
   std::vector<Inst> inst;
+  // graph replay of Arnoldi steps (rsfde_set_graph)
+  bool graphs = false;
+  hipStream_t cap = nullptr;             // private stream the steps are captured on
+  std::vector<hipGraphExec_t> bgexec;    // batched steps captured on the full-set plan
+  long long plan_gen = 0, bg_gen = -1;   // full-set plan generation the batched graphs belong to
   // batched engine (count > 1)
   bool batched = false;
   char* bdev = nullptr;          // descriptor buffer in the workspace
@@ -692,6 +699,43 @@ static int read_summary(rsfde_ctx* h, const Inst& I, GmresSummary* out) {
 // cycle's iteration count, then one step at a time.  Kernels of steps past
 // convergence exit on the device status (FL); the update kernel that closes a
 // chunk resolves its last step and adds V y once the cycle has finished.
+// Replay of one Arnoldi step from a graph captured on the private stream: the
+// step's launches have fixed arguments for a given (j, pending resolve), so
+// they are captured once and replayed on the handle's stream.  Used when graph
+// replay is on and no kernel class is being timed (event-stamped dispatches stay
+// outside graphs).
+template <typename Fn>
+static int graph_step(rsfde_ctx* h, std::vector<hipGraphExec_t>& cache, size_t slot, Fn launch) {
+  if (cache.size() <= slot) cache.resize(slot + 1, nullptr);
+  if (!cache[slot]) {
+    hipStream_t saved = h->stream;
+    h->stream = h->cap;
+    CK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    const int st = launch();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    h->stream = saved;
+    if (st < 0) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    CK(e);
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    CK(ei);
+    cache[slot] = x;
+  }
+  CK(hipGraphLaunch(cache[slot], h->stream));
+  return RSFDE_OK;
+}
+
+static void graphs_clear(std::vector<hipGraphExec_t>& cache) {
+  for (auto& x : cache)
+    if (x) (void)hipGraphExecDestroy(x);
+  cache.clear();
+}
+
 static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* S) {
   const int m = I.p.restart;
   const int nb = kry_blocks(I.n);
@@ -701,34 +745,48 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
   while (true) {
     const int jend = std::min(m, j + chunk);
     for (int jj = j; jj < jend; ++jj) {
-      double* vj = I.V + (int64_t)jj * I.ldv;
-      double* w = I.V + (int64_t)(jj + 1) * I.ldv;
-      GmRes g;
-      g.st = I.st;
-      g.p3 = I.pk[2];
-      g.nb3 = nb;
-      g.j = jj;
-      g.pend = jj == j ? pending : jj - 1;
-      g.m = m;
-      CKS(run_chain(h, I, CH_OPER, fp32, vj, nullptr, nullptr, 0.0, w, &g, &I.st->FL[jj]));
-      KryArgs ka;
-      ka.V = I.V;
-      ka.ldv = I.ldv;
-      ka.n = I.n;
-      ka.w = w;
-      ka.st = I.st;
-      ka.pa = I.pk[0];
-      ka.pb = I.pk[1];
-      ka.pc = I.pk[2];
-      ka.j = jj;
-      ka.m = m;
-      const double vb = 8.0 * (double)I.n;
-      CKS(timed_launch(h, RSFDE_K_DOTS, vb * (jj + 2),
-                       [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(1, ka, h->stream, ea, eb); }));
-      CKS(timed_launch(h, RSFDE_K_ORTH_DOTS, vb * (jj + 3),
-                       [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(2, ka, h->stream, ea, eb); }));
-      CKS(timed_launch(h, RSFDE_K_ORTH_NORM, vb * (jj + 3),
-                       [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(3, ka, h->stream, ea, eb); }));
+      const int pend = jj == j ? pending : jj - 1;
+      auto launch = [&]() -> int {
+        double* vj = I.V + (int64_t)jj * I.ldv;
+        double* w = I.V + (int64_t)(jj + 1) * I.ldv;
+        GmRes g;
+        g.st = I.st;
+        g.p3 = I.pk[2];
+        g.nb3 = nb;
+        g.j = jj;
+        g.pend = pend;
+        g.m = m;
+        CKS(run_chain(h, I, CH_OPER, fp32, vj, nullptr, nullptr, 0.0, w, &g, &I.st->FL[jj]));
+        KryArgs ka;
+        ka.V = I.V;
+        ka.ldv = I.ldv;
+        ka.n = I.n;
+        ka.w = w;
+        ka.st = I.st;
+        ka.pa = I.pk[0];
+        ka.pb = I.pk[1];
+        ka.pc = I.pk[2];
+        ka.j = jj;
+        ka.m = m;
+        const double vb = 8.0 * (double)I.n;
+        CKS(timed_launch(h, RSFDE_K_DOTS, vb * (jj + 2),
+                         [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(1, ka, h->stream, ea, eb); }));
+        CKS(timed_launch(h, RSFDE_K_ORTH_DOTS, vb * (jj + 3),
+                         [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(2, ka, h->stream, ea, eb); }));
+        CKS(timed_launch(h, RSFDE_K_ORTH_NORM, vb * (jj + 3),
+                         [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(3, ka, h->stream, ea, eb); }));
+        return RSFDE_OK;
+      };
+      if (h->graphs && h->tmask == 0) {
+        const void* ek = fp32 ? (const void*)I.e32 : (const void*)I.ecur;
+        if (ek != I.g_e) {
+          graphs_clear(I.gexec);
+          I.g_e = ek;
+        }
+        CKS(graph_step(h, I.gexec, (size_t)(2 * jj + (pend >= 0 ? 1 : 0)), launch));
+      } else {
+        CKS(launch());
+      }
     }
     GmRes gu;
     gu.st = I.st;
@@ -1091,13 +1149,26 @@ static int run_cycle_batched(rsfde_ctx* h, const std::vector<int>& S, bool fp32,
     const int m = bp.kp.m;
     const int jend = std::min(m, j + chunk);
     for (int jj = j; jj < jend; ++jj) {
-      CKS(launch_chain_batched(h, bp.oper, jj, jj == j ? pending : jj - 1));
-      for (int w = 1; w <= 3; ++w) {
-        const KLaunch kl = klaunch(bp.kp, false, jj, -1, 0, nullptr);
-        const int cls = w == 1 ? RSFDE_K_DOTS : (w == 2 ? RSFDE_K_ORTH_DOTS : RSFDE_K_ORTH_NORM);
-        CKS(timed_launch(h, cls, bp.kp.vbytes * (jj + 2 + (w > 1 ? 1 : 0)), [&](hipEvent_t ea, hipEvent_t eb) {
-          return kry_sweep_batched(w, kl, bp.kp.nb_total, h->stream, ea, eb);
-        }));
+      const int pend = jj == j ? pending : jj - 1;
+      auto launch = [&]() -> int {
+        CKS(launch_chain_batched(h, bp.oper, jj, pend));
+        for (int w = 1; w <= 3; ++w) {
+          const KLaunch kl = klaunch(bp.kp, false, jj, -1, 0, nullptr);
+          const int cls = w == 1 ? RSFDE_K_DOTS : (w == 2 ? RSFDE_K_ORTH_DOTS : RSFDE_K_ORTH_NORM);
+          CKS(timed_launch(h, cls, bp.kp.vbytes * (jj + 2 + (w > 1 ? 1 : 0)), [&](hipEvent_t ea, hipEvent_t eb) {
+            return kry_sweep_batched(w, kl, bp.kp.nb_total, h->stream, ea, eb);
+          }));
+        }
+        return RSFDE_OK;
+      };
+      if (h->graphs && h->tmask == 0 && &bp == &h->full) {
+        if (h->bg_gen != h->plan_gen) {
+          graphs_clear(h->bgexec);
+          h->bg_gen = h->plan_gen;
+        }
+        CKS(graph_step(h, h->bgexec, (size_t)(2 * jj + (pend >= 0 ? 1 : 0)), launch));
+      } else {
+        CKS(launch());
       }
     }
     const KLaunch ku = klaunch(bp.kp, true, jend - 1, jend - 1, 0, h->dmask);
@@ -1152,6 +1223,7 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
     CKS(build_plans(h, 0, act, u, f_half, true, mixed, h->full));
     h->full_key = key;
     h->full_valid = true;
+    ++h->plan_gen;  // graphs captured on the previous plan are stale
   }
   BPlan& bp0 = h->full;
   CK(compute_F_batched(bp0.fjobs, bp0.fstart, bp0.nf, bp0.fblocks, h->stream));
@@ -1618,6 +1690,9 @@ int rsfde_destroy(rsfde_handle h) {
     (void)hipEventDestroy(tp.b);
   }
   for (auto ev : h->ev_free) (void)hipEventDestroy(ev);
+  for (auto& I : h->inst) graphs_clear(I.gexec);
+  graphs_clear(h->bgexec);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->bhost) (void)hipHostFree(h->bhost);
   if (h->psum) (void)hipHostFree(h->psum);
@@ -1824,6 +1899,18 @@ int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* 
   if (s) CK(hipMemcpy(s, A.s, A.N * sizeof(double), hipMemcpyDeviceToHost));
   if (q) CK(hipMemcpy(q, A.q, A.N * sizeof(double), hipMemcpyDeviceToHost));
   if (lambda) CK(hipMemcpy(lambda, A.lam64, A.N * sizeof(double), hipMemcpyDeviceToHost));
+  return RSFDE_OK;
+}
+
+int rsfde_set_graph(rsfde_handle h, int enable) {
+  if (!h || (enable != 0 && enable != 1)) return RSFDE_E_INVALID_ARG;
+  if (enable && !h->cap) CK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  if (!enable) {
+    CK(hipStreamSynchronize(h->stream));
+    for (auto& I : h->inst) graphs_clear(I.gexec);
+    graphs_clear(h->bgexec);
+  }
+  h->graphs = enable != 0;
   return RSFDE_OK;
 }
 

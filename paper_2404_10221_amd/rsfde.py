@@ -36,7 +36,7 @@ WHICH_E, WHICH_F, WHICH_PSI = 0, 1, 2
 EXPORTED = (
     "rsfde_workspace_size", "rsfde_setup", "rsfde_set_ebar", "rsfde_step", "rsfde_solve",
     "rsfde_destroy", "rsfde_strerror", "rsfde_set_fields", "rsfde_eval_field",
-    "rsfde_eval_field_batch", "rsfde_apply_A",
+    "rsfde_eval_field_batch", "rsfde_set_graph", "rsfde_apply_A",
     "rsfde_apply_prec", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
     "rsfde_get_timing", "rsfde_prescan_ebar",
 )
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_rhs.argtypes = [P, I, P, P, P, P]
     lib.rsfde_get_tables.argtypes = [P, I, I, P, P, P]
     lib.rsfde_set_timing.argtypes = [P, C.c_uint, I]
+    lib.rsfde_set_graph.argtypes = [P, I]
     lib.rsfde_get_timing.argtypes = [P, I, C.POINTER(C.c_longlong), C.POINTER(D), C.POINTER(D)]
     lib.rsfde_prescan_ebar.argtypes = [P, I, I]
     for name in EXPORTED:
@@ -271,6 +272,10 @@ def rsfde_get_tables(h, instance: int, axis: int, N: int):
     _check(load_library().rsfde_get_tables(h, instance, axis, s.ctypes.data, q.ctypes.data, lam.ctypes.data),
            "rsfde_get_tables")
     return s, q, lam
+
+
+def rsfde_set_graph(h, enable: bool) -> None:
+    _check(load_library().rsfde_set_graph(h, 1 if enable else 0), "rsfde_set_graph")
 
 
 def rsfde_set_timing(h, mask: int, every: int = 1) -> None:

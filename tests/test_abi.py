@@ -103,6 +103,7 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.rsfde_set_ebar(None, 0, 1.0, 2.0) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_apply_A(None, 0, None, None, None) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_set_timing(None, 1, 1) == R.RSFDE_E_INVALID_ARG
+    assert lib.rsfde_set_graph(None, 1) == R.RSFDE_E_INVALID_ARG
 
 
 def test_params_from_paper_example():
