@@ -1,6 +1,7 @@
 """FP64 CPU oracle: quasi-compact Crank-Nicolson scheme for the variable-coefficient
 Riesz space-fractional diffusion equation, solved at every step by GMRES(m) with
-the sine-transform (tau) preconditioner, one-sided form.
+the sine-transform (tau) preconditioner: the one-sided form (eq. one-sided) and
+the two-sided form (eq. Pls).
 
 TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
 cpu_baseline leg of bench.py may import or call this module.  It is written from
@@ -23,6 +24,9 @@ Readings of points the paper leaves open (each also listed in the design notes):
     ||z_k||_2 <= tol ||z_0||_2 for the left-preconditioned residual z, restarts
     every `restart` iterations keeping ||z_0|| of the step as the reference.
   * The L2 error of Table 1 is max_m sqrt(prod_i h_i * sum_J (u*-u)^2).
+  * Two-sided form: GMRES with no further preconditioner on eq. Pls, started from
+    utilde_0 = P^{1/2} u^{(m)} (the image of the one-sided start), with the same
+    stopping rule on its own residual; u^{(m+1)} = P^{-1/2} utilde.
 """
 from __future__ import annotations
 
@@ -394,6 +398,44 @@ class OracleProblem:
             self._mu = mu
         return self._mu
 
+    # -- two-sided form (eqs. equi, Pa, Pls)
+    def lam_K(self) -> np.ndarray:
+        """Eigenvalues of B_alpha = B_{alpha_d} x ... x B_{alpha_1} in the sine basis
+        (Lemma Heig; products of the per-axis eigenvalues)."""
+        lamK = np.ones(self.shape)
+        for i in range(self.d):
+            lamK = lamK * self.lam[i].reshape([-1 if a == self.d - 1 - i else 1 for a in range(self.d)])
+        return lamK
+
+    def tauS_eigs(self) -> np.ndarray:
+        """Eigenvalues of tau(S_alpha) (eq. tauSalpha) in the sine basis: each Kronecker
+        term contributes eta_i q_i times the B eigenvalues of the other axes."""
+        out = np.zeros(self.shape)
+        for i in range(self.d):
+            term = np.ones(self.shape) * self.eta[i]
+            for l in range(self.d):
+                v = self.q[l] if l == i else self.lam[l]
+                term = term * v.reshape([-1 if a == self.d - 1 - l else 1 for a in range(self.d)])
+            out = out + term
+        return out
+
+    def P_eigs(self) -> np.ndarray:
+        """Eigenvalues of P_alpha = ebar I + B^{-1/2} tau(S_alpha) B^{-1/2} (eq. Pa): the
+        sine transform diagonalises B_alpha and tau(S_alpha) together (eq. diag)."""
+        return self.ebar + self.tauS_eigs() / self.lam_K()
+
+    def apply_B_inv(self, X: np.ndarray) -> np.ndarray:
+        """B_alpha^{-1} x through its sine diagonalisation (eq. diag)."""
+        return self.apply_sine(self.apply_sine(X) / self.lam_K())
+
+    def apply_P_power(self, X: np.ndarray, power: float) -> np.ndarray:
+        """P_alpha^{power} x = S diag(p_K^{power}) S x (eq. Pa, eq. diag)."""
+        return self.apply_sine(self.apply_sine(X) * self.P_eigs() ** power)
+
+    def apply_Atilde(self, e: np.ndarray, X: np.ndarray) -> np.ndarray:
+        """Atilde = E + B_alpha^{-1} S_alpha (eq. equi)."""
+        return e * X + self.apply_B_inv(self.apply_S(X))
+
     def apply_sine(self, X: np.ndarray) -> np.ndarray:
         Y = X
         for i in range(self.d):
@@ -441,6 +483,29 @@ class OracleProblem:
                            rtol=self.inst.rtol if rtol is None else rtol,
                            max_cycles=self.inst.max_cycles if max_cycles is None else max_cycles)
         return x, st
+
+
+    def step_two_sided(self, u: np.ndarray, m: int, x0_mode: int = 0,
+                       restart: Optional[int] = None, rtol: Optional[float] = None,
+                       max_cycles: Optional[int] = None):
+        """One step through the two-sided system (eq. Pls): GMRES on
+        P^{-1/2} Atilde P^{-1/2} utilde = P^{-1/2} btilde with btilde = B^{-1} b
+        (eq. equi) and utilde = P^{1/2} u; then u^{(m+1)} = P^{-1/2} utilde."""
+        th = self.t_half(m)
+        e = self.e_at(th)
+        F = self.F_from_closure(self.f_closure_at(th))
+        b = self.rhs(e, F, u)
+        rhs = self.apply_P_power(self.apply_B_inv(b), -0.5)
+
+        def op(v):
+            return self.apply_P_power(self.apply_Atilde(e, self.apply_P_power(v, -0.5)), -0.5)
+
+        x0 = self.apply_P_power(u, 0.5) if x0_mode == 0 else np.zeros_like(u)
+        xt, st = gmres_left(op, lambda r: r, rhs, x0,
+                            restart=self.inst.restart if restart is None else restart,
+                            rtol=self.inst.rtol if rtol is None else rtol,
+                            max_cycles=self.inst.max_cycles if max_cycles is None else max_cycles)
+        return self.apply_P_power(xt, -0.5), st
 
 
 # ----------------------------------------------------------------------------
@@ -520,16 +585,21 @@ def gmres_left(apply_A: Callable, apply_Minv: Callable, b: np.ndarray, x0: np.nd
 
 def run(inst, steps: Optional[int] = None, ebar: Optional[float] = None, x0_mode: int = 0,
         u0: Optional[np.ndarray] = None, m0: int = 0, track_error: bool = False,
-        callback: Optional[Callable] = None) -> Dict:
+        callback: Optional[Callable] = None, two_sided: bool = False) -> Dict:
     """Run `steps` Crank-Nicolson steps (default: all M) from u0 (default psi) starting
-    at step index m0.  Returns the final u (flat, x_1 fastest) and per-step stats."""
+    at step index m0, each solved in the one-sided form (eq. one-sided) or, with
+    two_sided, in the two-sided form (eq. Pls).  Returns the final u (flat, x_1
+    fastest) and per-step stats."""
     P = OracleProblem(inst, ebar=ebar)
     u = P.psi() if u0 is None else np.asarray(u0, dtype=np.float64).reshape(P.shape).copy()
     steps = inst.M - m0 if steps is None else steps
     iters = []
     err = 0.0
     for m in range(m0, m0 + steps):
-        u, st = P.step(u, m, x0_mode=x0_mode)
+        if two_sided:
+            u, st = P.step_two_sided(u, m, x0_mode=x0_mode)
+        else:
+            u, st = P.step(u, m, x0_mode=x0_mode)
         iters.append(st["iters"])
         if callback is not None:
             callback(m, u, st)

