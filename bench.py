@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-two-sided", action="store_true",
+                    help="skip the run of the two-sided form (eq. Pls)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="skip the run with graph replay of the Arnoldi steps")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -320,6 +322,25 @@ def main():
                         "gmres_iters_per_step": (gm.iters - it0) / K,
                         "rel_diff_vs_fp64_gpu": diff, "status": gm.status}
         gm.close()
+
+    # ---- two-sided form (eq. Pls, FP64) on the same steps: more passes per iteration
+    if not args.no_two_sided:
+        gt = Stepper(insts, method=R.RSFDE_TPGM)
+        for _ in range(W):
+            gt.step()
+        it0 = gt.iters
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            gt.step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        diff = max(float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+                   for a, b in zip(gt.us, u64))
+        out["two_sided"] = {"value": K / el, "unit": "time-steps/s", "ms_per_step": 1e3 * el / K,
+                            "gmres_iters_per_step": (gt.iters - it0) / K,
+                            "rel_diff_vs_one_sided_gpu": diff, "status": gt.status}
+        gt.close()
 
     # ---- FP64 form with graph replay of the Arnoldi steps (no kernel timing)
     if not args.no_graphs:

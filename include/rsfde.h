@@ -65,6 +65,18 @@ extern "C" {
 #define RSFDE_MIXED  1  /* FP32 operator/preconditioner inside GMRES, FP64 Arnoldi,
                            Givens and norms, FP64 true-residual iterative refinement */
 
+/* ---- solver forms (Section 3) ---------------------------------------------
+ * With Atilde = E + B_alpha^{-1} S_alpha and btilde = B_alpha^{-1} b (eq. equi) and
+ * the tau preconditioner P_alpha (eq. Pa):
+ *   RSFDE_OPGM  GMRES on P^{-1} Atilde u = P^{-1} btilde (eq. one-sided), run as
+ *               (B P)^{-1} A u = (B P)^{-1} b, which is the same system;
+ *   RSFDE_TPGM  GMRES on P^{-1/2} Atilde P^{-1/2} utilde = P^{-1/2} btilde (eq. Pls),
+ *               started from utilde_0 = P^{1/2} u^{(m)} (or 0) and stopped on its own
+ *               residual; u^{(m+1)} = P^{-1/2} utilde.  FP64 only; instances of this
+ *               form are stepped one at a time (no batched launches). */
+#define RSFDE_OPGM  0
+#define RSFDE_TPGM  1
+
 typedef struct rsfde_ctx* rsfde_handle;
 
 /* One problem instance.  Fields beyond the paper's statement are solver settings. */
@@ -84,6 +96,8 @@ typedef struct {
   int     x0_mode;      /* 0: GMRES starts from u^{(m)}; 1: from zero */
   double  inner_rtol;   /* RSFDE_MIXED: tolerance of each FP32 inner solve (0 -> 1e-5) */
   int     max_outer;    /* RSFDE_MIXED: refinement sweeps allowed per step (0 -> 30) */
+  int     method;       /* RSFDE_OPGM (0) or RSFDE_TPGM; RSFDE_TPGM with RSFDE_MIXED is
+                           RSFDE_E_UNSUPPORTED */
 } rsfde_params;
 
 /* Per-instance result of one step (summed over the steps of rsfde_solve). */
@@ -195,6 +209,18 @@ int rsfde_apply_A(rsfde_handle h, int instance, const double* e, const double* v
 /* out = (B_alpha P_alpha)^{-1} r = S diag(1/mu) S r, the sine-transform solve with the
  * tau preconditioner (eqs. Pa, tauSalpha, diag); needs ebar to be set. */
 int rsfde_apply_prec(rsfde_handle h, int instance, const double* r, double* out);
+
+/* out = S diag(g) S r for one of the sine-basis diagonals g of Section 3, with
+ * Lambda_K the eigenvalues of B_alpha and mu_K those of B_alpha P_alpha:
+ *   RSFDE_PREC_BP_INV     (B_alpha P_alpha)^{-1}       g = 1/mu      (as rsfde_apply_prec)
+ *   RSFDE_PREC_PHALF_BINV P_alpha^{-1/2} B_alpha^{-1}  g = 1/sqrt(Lambda mu)   (eq. Pls)
+ *   RSFDE_PREC_PHALF      P_alpha^{-1/2}               g = sqrt(Lambda / mu)   (eq. Pls)
+ * r and out: FP64 device vectors of the instance's size, not overlapping; needs ebar.
+ * Errors: RSFDE_E_INVALID_ARG (bad form, null pointer), RSFDE_E_STATE, RSFDE_E_HIP. */
+#define RSFDE_PREC_BP_INV      0
+#define RSFDE_PREC_PHALF_BINV  1
+#define RSFDE_PREC_PHALF       2
+int rsfde_apply_prec_form(rsfde_handle h, int instance, int form, const double* r, double* out);
 
 /* out = F = (H_{alpha_d} ... H_{alpha_1}) f restricted to the interior, from f on the
  * closure grid (eq. eq2.2, Appendix A). */

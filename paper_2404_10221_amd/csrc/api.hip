@@ -318,6 +318,8 @@ static int validate(const rsfde_params* p) {
   if (p->x0_mode != 0 && p->x0_mode != 1) return RSFDE_E_INVALID_ARG;
   if (!(p->inner_rtol >= 0.0 && p->inner_rtol < 1.0)) return RSFDE_E_INVALID_ARG;
   if (p->max_outer < 0) return RSFDE_E_INVALID_ARG;
+  if (p->method != RSFDE_OPGM && p->method != RSFDE_TPGM) return RSFDE_E_INVALID_ARG;
+  if (p->method == RSFDE_TPGM && p->precision != RSFDE_FP64) return RSFDE_E_UNSUPPORTED;
   if (n > ((int64_t)1 << 34)) return RSFDE_E_INVALID_ARG;
   for (int i = 0; i < p->d; ++i) {
     const int64_t L = 2 * (p->n[i] + 1);
@@ -489,22 +491,85 @@ static int flush_timing(rsfde_ctx* h) {
   return RSFDE_OK;
 }
 
+// Transform, diagonal scaling (PM_*), transform for an FP64 r: (BP)^{-1} r, or
+// a factor of the two-sided form.  Temporaries T[0], T[1], T[2], T[3] in turn
+// (d = 3); out may be T[2], r may be T[3].
+static int run_prec(rsfde_ctx* h, const Inst& I, bool fp32, const double* r, double* out,
+                    int pmode = PM_BP_INV, const int* stop_fl = nullptr) {
+  const int d = I.d;
+  void* const* T = I.tmp;
+  if (d == 1) {
+    PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
+    t.flags = FL_IN64 | FL_OUT64;
+    t.in_c = r;
+    t.out_a = out;
+    t.pmode = pmode;
+    t.stop_fl = stop_fl;
+    return run_pass(h, I, t, fp32);
+  }
+  int cur = -1;
+  for (int ax = d - 1; ax >= 1; --ax) {
+    PassArgs t = mk_pass(I, ax, OP_DST, fp32);
+    t.flags = cur < 0 ? FL_IN64 : 0;
+    t.in_c = cur < 0 ? (const void*)r : T[cur];
+    const int o = cur < 0 ? 0 : (cur + 1) & 3;
+    t.out_a = T[o];
+    t.stop_fl = stop_fl;
+    CKS(run_pass(h, I, t, fp32));
+    cur = o;
+  }
+  {
+    PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
+    t.in_c = T[cur];
+    const int o = (cur + 1) & 3;
+    t.out_a = T[o];
+    t.pmode = pmode;
+    t.stop_fl = stop_fl;
+    CKS(run_pass(h, I, t, fp32));
+    cur = o;
+  }
+  for (int ax = 1; ax <= d - 1; ++ax) {
+    PassArgs t = mk_pass(I, ax, OP_DST, fp32);
+    t.in_c = T[cur];
+    const bool last = ax == d - 1;
+    const int o = (cur + 1) & 3;
+    t.flags = last ? FL_OUT64 : 0;
+    t.out_a = last ? (void*)out : T[o];
+    t.stop_fl = stop_fl;
+    CKS(run_pass(h, I, t, fp32));
+    cur = o;
+  }
+  return RSFDE_OK;
+}
+
 enum Chain { CH_APPLY_A = 0, CH_RHS = 1, CH_RESID = 2, CH_OPER = 3 };
 
 // Operator chains along the axes (x_1 first).  CH_APPLY_A: out = A x.
-// CH_RHS: out = B E x - S x + xcoef * xin.  CH_RESID: out = (BP)^{-1}(xin - A x).
-// CH_OPER: out = (BP)^{-1} A (sc * x).  x is FP64; out is FP64.
+// CH_RHS: out = B E x - S x + xcoef * xin.  CH_RESID: out = M (xin - A x).
+// CH_OPER: out = M A (sc * x).  M = (BP)^{-1} in the one-sided form; in the
+// two-sided form (eq. Pls) M = P^{-1/2} B^{-1} and CH_OPER first takes x to
+// P^{-1/2} x (into T[2]; the step's scale is applied when the next pass reads
+// it).  x is FP64; out is FP64.
 static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const double* x,
                      const double* sc, const double* xin, double xcoef, double* out,
                      const GmRes* gm = nullptr, const int* stop_fl = nullptr) {
   const int d = I.d;
   const void* e = fp32 ? (const void*)I.e32 : (const void*)I.ecur;
   const bool prec = kind == CH_RESID || kind == CH_OPER;
+  const bool two = I.p.method == RSFDE_TPGM;
+  const int pm = two ? PM_PH_BINV : PM_BP_INV;
+  if (two && kind == CH_OPER) {
+    // runs before the step's resolve: exit on the status before the pending step
+    const int* pre_stop = gm ? &I.st->FL[gm->pend >= 0 ? gm->pend : gm->j] : stop_fl;
+    CKS(run_prec(h, I, fp32, x, (double*)I.tmp[2], PM_PH, pre_stop));
+    x = (const double*)I.tmp[2];
+  }
   const double sgn = kind == CH_RHS ? -1.0 : 1.0;
   void* const* T = I.tmp;
   if (d == 1) {
     PassArgs a = mk_pass(I, 0, OP_MV_LAST, fp32);
     a.flags = FL_FIRST_IS_LAST | FL_IN64 | FL_OUT64 | (prec ? FL_PREC_FULL : 0);
+    a.pmode = pm;
     a.in_c = x;
     a.sc_ptr = sc;
     a.in_a = e;
@@ -581,6 +646,7 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
     t.in_c = T[cur];
     t.out_a = T[nxt(cur)];
     t.stop_fl = stop_fl;
+    t.pmode = pm;
     CKS(run_pass(h, I, t, fp32));
     cur = nxt(cur);
   }
@@ -593,48 +659,6 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
     t.out_a = last ? (void*)out : T[nxt(cur)];
     CKS(run_pass(h, I, t, fp32));
     cur = nxt(cur);
-  }
-  return RSFDE_OK;
-}
-
-// (BP)^{-1} r for an FP64 r.
-static int run_prec(rsfde_ctx* h, const Inst& I, bool fp32, const double* r, double* out) {
-  const int d = I.d;
-  void* const* T = I.tmp;
-  if (d == 1) {
-    PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
-    t.flags = FL_IN64 | FL_OUT64;
-    t.in_c = r;
-    t.out_a = out;
-    return run_pass(h, I, t, fp32);
-  }
-  int cur = -1;
-  for (int ax = d - 1; ax >= 1; --ax) {
-    PassArgs t = mk_pass(I, ax, OP_DST, fp32);
-    t.flags = cur < 0 ? FL_IN64 : 0;
-    t.in_c = cur < 0 ? (const void*)r : T[cur];
-    const int o = cur < 0 ? 0 : (cur + 1) & 3;
-    t.out_a = T[o];
-    CKS(run_pass(h, I, t, fp32));
-    cur = o;
-  }
-  {
-    PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
-    t.in_c = T[cur];
-    const int o = (cur + 1) & 3;
-    t.out_a = T[o];
-    CKS(run_pass(h, I, t, fp32));
-    cur = o;
-  }
-  for (int ax = 1; ax <= d - 1; ++ax) {
-    PassArgs t = mk_pass(I, ax, OP_DST, fp32);
-    t.in_c = T[cur];
-    const bool last = ax == d - 1;
-    const int o = (cur + 1) & 3;
-    t.flags = last ? FL_OUT64 : 0;
-    t.out_a = last ? (void*)out : T[o];
-    CKS(run_pass(h, I, t, fp32));
-    cur = o;
   }
   return RSFDE_OK;
 }
@@ -795,11 +819,22 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
     gu.j = jend - 1;
     gu.pend = jend - 1;
     gu.m = m;
+    // two-sided form: the update V y lands in T[3] (zeroed first) and
+    // u += P^{-1/2} (V y) once the cycle has ended
+    const bool two = I.p.method == RSFDE_TPGM;
+    double* xu = two ? (double*)I.tmp[3] : x;
+    if (two) CK(fill_f64(xu, I.n, 0.0, h->stream));
     CKS(timed_launch(h, RSFDE_K_UPDATE, 0.0, [&](hipEvent_t ea, hipEvent_t eb) {
-      return kry_update(I.V, I.ldv, I.n, x, gu, h->stream, ea, eb);
+      return kry_update(I.V, I.ldv, I.n, xu, gu, h->stream, ea, eb);
     }));
     CKS(read_summary(h, I, S));
-    if (S->flag != GM_RUNNING) return RSFDE_OK;
+    if (S->flag != GM_RUNNING) {
+      if (two && S->flag != GM_NONFINITE) {
+        CKS(run_prec(h, I, fp32, xu, (double*)I.tmp[2], PM_PH));
+        CK(axpy_f64((const double*)I.tmp[2], x, I.n, h->stream));
+      }
+      return RSFDE_OK;
+    }
     j = jend;
     pending = -1;
     chunk = 1;
@@ -887,7 +922,7 @@ static bool batchable(const rsfde_ctx* h) {
   // addresses exist in every instance)
   for (const Inst& I : h->inst)
     if (I.d != h->inst[0].d || I.p.precision != h->inst[0].p.precision ||
-        I.p.restart != h->inst[0].p.restart)
+        I.p.restart != h->inst[0].p.restart || I.p.method != RSFDE_OPGM)
       return false;
   return true;
 }
@@ -1872,6 +1907,16 @@ int rsfde_apply_prec(rsfde_handle h, int instance, const double* r, double* out)
   Inst& I = h->inst[instance];
   if (!I.ebar_set) return RSFDE_E_STATE;
   return run_prec(h, I, false, r, out);
+}
+
+int rsfde_apply_prec_form(rsfde_handle h, int instance, int form, const double* r, double* out) {
+  if (!h || instance < 0 || instance >= h->count || !r || !out) return RSFDE_E_INVALID_ARG;
+  if (form != RSFDE_PREC_BP_INV && form != RSFDE_PREC_PHALF_BINV && form != RSFDE_PREC_PHALF)
+    return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  if (!I.ebar_set) return RSFDE_E_STATE;
+  const int pm = form == RSFDE_PREC_BP_INV ? PM_BP_INV : (form == RSFDE_PREC_PHALF_BINV ? PM_PH_BINV : PM_PH);
+  return run_prec(h, I, false, r, out, pm);
 }
 
 int rsfde_compute_F(rsfde_handle h, int instance, const double* f_closure, double* out) {

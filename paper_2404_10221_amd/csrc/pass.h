@@ -6,7 +6,8 @@
 //     inverse FFT, keep the first N_i entries,
 //   * the type-I sine transform (Section 3, eq. diag) through the FFT of the odd
 //     extension [0, x_1..x_N, 0, -x_N..-x_1] of length L,
-//   * the diagonal 1/mu_K scaling of the tau preconditioner in the sine basis.
+//   * a diagonal scaling in the sine basis: 1/mu_K of the tau preconditioner,
+//     or the factors of the two-sided form (eq. Pls).
 // Two real pencils are packed as the real and imaginary parts of one complex
 // transform.  Operators along different axes commute, so the d-dimensional
 // matvec A v = B_alpha E v + S_alpha v and the preconditioner solve are chains of
@@ -21,6 +22,12 @@
 #include "krylov.h"
 
 enum : int { OP_MV_FIRST = 0, OP_MV_MID = 1, OP_MV_LAST = 2, OP_DST = 3, OP_DSD = 4 };
+// Diagonal of the scale phase in the sine basis, with Lambda_K the eigenvalues of
+// B_alpha and mu_K = Lambda_K (ebar + sum_i eta_i q_i / lambda_i) those of B_alpha P_alpha:
+//   PM_BP_INV     1/mu                  (B P)^{-1}            (eq. one-sided)
+//   PM_PH_BINV    1/sqrt(Lambda mu)     P^{-1/2} B^{-1}       (eq. Pls, left factor)
+//   PM_PH         sqrt(Lambda / mu)     P^{-1/2}              (eq. Pls, right factor)
+enum : int { PM_BP_INV = 0, PM_PH_BINV = 1, PM_PH = 2 };
 enum : int {
   FL_DST_AFTER = 1,      // MV_LAST: follow by a sine transform along the same axis
   FL_PREC_FULL = 2,      // MV_LAST (d = 1): follow by transform, 1/mu scaling, transform
@@ -56,6 +63,7 @@ struct PassArgs {
   const void* wq[3];     // eta_i q_i / lambda_i per axis (precision R)
   const double* ebar;    // device scalar ebar
   double pscale;         // prod_i 1/L_i: normalisation of the two sine transforms
+  int pmode;             // scaling of the scale phase (PM_*)
   int var;               // host only: workgroup-shape variant
   int use_gm;            // first operator pass of an Arnoldi step: resolve the previous step
   GmRes gm;              // (input scale = vsc[j] from that resolve; exit when the cycle ended)
@@ -512,9 +520,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   (void)dst_phase;
   fft_lds<R, L, -1>(buf, t, tw);
   if (scale_phase) {
-    // 1/mu_K in the sine basis (eq. Pa, Lemma le:eig, Lemma Heig, eq. q); the
-    // pass runs along axis 0, the other axes are already transformed.
+    // 1/mu_K in the sine basis (eq. Pa, Lemma le:eig, Lemma Heig, eq. q), or a
+    // two-sided factor (PM_*); the pass runs along axis 0, the other axes are
+    // already transformed.
     const R ps = (R)a.pscale;
+    const int pm = a.pmode;
     if constexpr (!STRIDED) {
       R eb, Lam[2], Sig[2], l0v[NE], w0v[NE];
       if (is_dsd) {
@@ -555,8 +565,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
         if (p < N) {
           const cpx<R> Z = buf[p + 1];
           const R l0 = l0v[i], w0 = w0v[i];
-          const R s0 = ps / (Lam[0] * l0 * (eb + w0 + Sig[0]));
-          const R s1 = ps / (Lam[1] * l0 * (eb + w0 + Sig[1]));
+          R g0 = eb + w0 + Sig[0], g1 = eb + w0 + Sig[1];  // mu / Lambda
+          if (pm != PM_BP_INV) {
+            g0 = sqrt(g0);
+            g1 = sqrt(g1);
+          }
+          const R s0 = ps / (pm == PM_PH ? g0 : Lam[0] * l0 * g0);
+          const R s1 = ps / (pm == PM_PH ? g1 : Lam[1] * l0 * g1);
           ra[i] = cpx<R>{-Z.y * s0, Z.x * s1};
         }
       }

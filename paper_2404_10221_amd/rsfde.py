@@ -26,6 +26,8 @@ RSFDE_E_STATE = -6
 
 RSFDE_FP64 = 0
 RSFDE_MIXED = 1
+RSFDE_OPGM, RSFDE_TPGM = 0, 1
+PREC_BP_INV, PREC_PHALF_BINV, PREC_PHALF = 0, 1, 2
 
 FIELD_KINDS = {
     "zero": 0, "const": 1, "sumsq_exp": 2, "poly_t": 3, "sinprod_cos": 4,
@@ -37,7 +39,7 @@ EXPORTED = (
     "rsfde_workspace_size", "rsfde_setup", "rsfde_set_ebar", "rsfde_step", "rsfde_solve",
     "rsfde_destroy", "rsfde_strerror", "rsfde_set_fields", "rsfde_eval_field",
     "rsfde_eval_field_batch", "rsfde_set_graph", "rsfde_apply_A",
-    "rsfde_apply_prec", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
+    "rsfde_apply_prec", "rsfde_apply_prec_form", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
     "rsfde_get_timing", "rsfde_prescan_ebar",
 )
 
@@ -50,7 +52,7 @@ class rsfde_params(C.Structure):
         ("alpha", C.c_double * 3), ("kappa", C.c_double * 3), ("dt", C.c_double),
         ("e_min", C.c_double), ("e_max", C.c_double), ("restart", C.c_int), ("rtol", C.c_double),
         ("max_cycles", C.c_int), ("precision", C.c_int), ("x0_mode", C.c_int),
-        ("inner_rtol", C.c_double), ("max_outer", C.c_int),
+        ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("method", C.c_int),
     ]
 
 
@@ -106,6 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_eval_field_batch.argtypes = [P, I, D, C.POINTER(P)]
     lib.rsfde_apply_A.argtypes = [P, I, P, P, P]
     lib.rsfde_apply_prec.argtypes = [P, I, P, P]
+    lib.rsfde_apply_prec_form.argtypes = [P, I, I, P, P]
     lib.rsfde_compute_F.argtypes = [P, I, P, P]
     lib.rsfde_rhs.argtypes = [P, I, P, P, P, P]
     lib.rsfde_get_tables.argtypes = [P, I, I, P, P, P]
@@ -144,7 +147,7 @@ def _stream(stream=None) -> int:
 
 def make_params(d, n, alpha, kappa, dt, *, lo=None, hi=None, e_min=0.0, e_max=0.0, restart=20,
                 rtol=1e-10, max_cycles=10, precision=RSFDE_FP64, x0_mode=0, inner_rtol=0.0,
-                max_outer=0) -> rsfde_params:
+                max_outer=0, method=0) -> rsfde_params:
     p = rsfde_params()
     p.d = int(d)
     for i in range(3):
@@ -158,6 +161,7 @@ def make_params(d, n, alpha, kappa, dt, *, lo=None, hi=None, e_min=0.0, e_max=0.
     p.restart, p.rtol, p.max_cycles = int(restart), float(rtol), int(max_cycles)
     p.precision, p.x0_mode = int(precision), int(x0_mode)
     p.inner_rtol, p.max_outer = float(inner_rtol), int(max_outer)
+    p.method = int(method)
     return p
 
 
@@ -254,6 +258,12 @@ def rsfde_apply_A(h, instance: int, e, v, out) -> None:
 
 def rsfde_apply_prec(h, instance: int, r, out) -> None:
     _check(load_library().rsfde_apply_prec(h, instance, _ptr(r), _ptr(out)), "rsfde_apply_prec")
+
+
+def rsfde_apply_prec_form(h, instance: int, form: int, r, out) -> None:
+    """form: PREC_BP_INV, PREC_PHALF_BINV or PREC_PHALF."""
+    _check(load_library().rsfde_apply_prec_form(h, instance, form, _ptr(r), _ptr(out)),
+           "rsfde_apply_prec_form")
 
 
 def rsfde_compute_F(h, instance: int, f_closure, out) -> None:

@@ -63,6 +63,8 @@ def _base(**over):
     (dict(max_cycles=0), R.RSFDE_E_INVALID_ARG),
     (dict(precision=2), R.RSFDE_E_INVALID_ARG),
     (dict(x0_mode=3), R.RSFDE_E_INVALID_ARG),
+    (dict(method=2), R.RSFDE_E_INVALID_ARG),
+    (dict(method=R.RSFDE_TPGM, precision=R.RSFDE_MIXED), R.RSFDE_E_UNSUPPORTED),
     (dict(lo=(0.0, 1.0), hi=(1.0, 1.0)), R.RSFDE_E_INVALID_ARG),
     (dict(n=(14, 15)), R.RSFDE_E_UNSUPPORTED),      # 2(N+1) = 30 is not 2^p or 3*2^p
     (dict(n=(4095, 15)), R.RSFDE_E_UNSUPPORTED),    # 2(N+1) = 8192 > 4096
@@ -104,6 +106,7 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.rsfde_apply_A(None, 0, None, None, None) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_set_timing(None, 1, 1) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_set_graph(None, 1) == R.RSFDE_E_INVALID_ARG
+    assert lib.rsfde_apply_prec_form(None, 0, 1, None, None) == R.RSFDE_E_INVALID_ARG
 
 
 def test_params_from_paper_example():

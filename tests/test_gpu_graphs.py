@@ -18,13 +18,14 @@ from gpu_helpers import empty, host, say
 pytestmark = pytest.mark.gpu
 
 
-def _run(insts, graphs, precision=R.RSFDE_FP64, fresh_e=False, timing_at=None, batched=True):
+def _run(insts, graphs, precision=R.RSFDE_FP64, fresh_e=False, timing_at=None, batched=True,
+         method=R.RSFDE_OPGM):
     """Step all instances through M steps with rsfde_step; returns per step the host
     copies of u and the iteration counts."""
     old = os.environ.get("RSFDE_NO_BATCH")
     os.environ["RSFDE_NO_BATCH"] = "0" if batched else "1"
     try:
-        S = R.Solver([R.params_from_instance(i, precision=precision) for i in insts])
+        S = R.Solver([R.params_from_instance(i, precision=precision, method=method) for i in insts])
     finally:
         if old is None:
             del os.environ["RSFDE_NO_BATCH"]
@@ -89,6 +90,15 @@ def test_graph_replay_new_e_buffers_and_timing_switches():
     inst = with_grid(config("C3"), (31, 31, 31), M=6)
     a = _run([inst], graphs=True, fresh_e=True, timing_at=(2, 4))
     b = _run([inst], graphs=False, fresh_e=True)
+    _same(a, b)
+
+
+@pytest.mark.parametrize("name,grid", [("C1", (63,)), ("C2", (47, 31)), ("C3", (15, 23, 11))])
+def test_graph_replay_two_sided(name, grid):
+    # the two-sided form's steps start with the P^{-1/2} passes
+    inst = replace(with_grid(config(name), grid, M=4), restart=4, max_cycles=60)
+    a = _run([inst], graphs=True, method=R.RSFDE_TPGM)
+    b = _run([inst], graphs=False, method=R.RSFDE_TPGM)
     _same(a, b)
 
 
