@@ -151,6 +151,7 @@ struct Inst {
   double* fmc = nullptr;
   double* fsin_e[3] = {nullptr, nullptr, nullptr};
   double* fsin_f[3] = {nullptr, nullptr, nullptr};
+  double* fax[3] = {nullptr, nullptr, nullptr};  // per-axis factor tables (AX_ROWS x (N_i+2))
   int k_prev = 4;
   std::vector<hipGraphExec_t> gexec;  // captured Arnoldi steps: [2 j + (resolve pending)]
   const void* g_e = nullptr;           // e the captured steps read
@@ -384,6 +385,7 @@ static void layout(Inst& I, Bump& B) {
   for (int i = 0; i < p.d; ++i) {
     I.fsin_e[i] = B.take<double>((size_t)RSFDE_MAXMODES * (p.n[i] + 2));
     I.fsin_f[i] = B.take<double>((size_t)RSFDE_MAXMODES * (p.n[i] + 2));
+    I.fax[i] = B.take<double>((size_t)AX_ROWS * (p.n[i] + 2));
   }
 }
 
@@ -679,6 +681,7 @@ static FieldDev field_dev(const Inst& I, const FieldHost& F, bool is_e) {
   fd.amp = is_e ? I.famp_e : I.famp_f;
   for (int i = 0; i < 3; ++i) fd.sintab[i] = i < I.d ? (is_e ? I.fsin_e[i] : I.fsin_f[i]) : nullptr;
   fd.mc = I.fmc;
+  for (int i = 0; i < 3; ++i) fd.ax[i] = i < I.d ? I.fax[i] : nullptr;
   return fd;
 }
 
@@ -1840,6 +1843,13 @@ int rsfde_set_fields(rsfde_handle h, int instance, const rsfde_field* e, const r
     }
   }
   CK(hipMemcpyAsync(I.fmc, mc.data(), mc.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  {
+    // one-coordinate factors of the separable fields, once per closure point
+    FieldDev fe = field_dev(I, I.fe, true), ff = field_dev(I, I.ff, false), fp = field_dev(I, I.fpsi, false);
+    fp.a = (int)llround(I.fpsi.spec.c[1]);
+    const GridDev gc = grid_dev(I, true);
+    for (int i = 0; i < d; ++i) CK(fields_axis_tables(fe, ff, fp, gc, i, I.fax[i], h->stream));
+  }
   CK(hipStreamSynchronize(h->stream));
   return RSFDE_OK;
 }

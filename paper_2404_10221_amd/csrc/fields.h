@@ -17,7 +17,13 @@ struct FieldDev {
   const double* amp;         // K^d amplitudes, k_1 fastest
   const double* sintab[3];   // sin((k+1) pi x_{i,j}) at [k*(N_i+2) + j], closure index j
   const double* mc;          // manufactured: per axis [left(13), right(13), sigma] at axis*32
+  const double* ax[3];       // per-axis factor tables (AX_* rows of N_i+2 entries, closure index)
 };
+
+// Rows of the per-axis tables: every factor of the separable fields that depends
+// on one coordinate only, evaluated once per closure point of the axis with the
+// same expression the point-wise evaluation would use.
+enum : int { AX_E = 0, AX_U = 1, AX_RIESZ = 2, AX_PSI = 3, AX_ROWS = 4 };
 
 struct GridDev {
   int d;
@@ -51,6 +57,9 @@ hipError_t fields_eval_batched(const FieldJob* jobs, const int* start, int n, in
 hipError_t compute_F_batched(const FJob* jobs, const int* start, int n, int64_t nblocks,
                              hipStream_t s);
 hipError_t fields_sintab(int K, int Ncl, double lo, double h, double* tab, hipStream_t s);
+// per-axis tables for axis `axis` of the closure grid g (E, F, psi as registered)
+hipError_t fields_axis_tables(const FieldDev& e, const FieldDev& f, const FieldDev& psi,
+                              const GridDev& g, int axis, double* tab, hipStream_t s);
 hipError_t compute_F(const double* fcl, const GridDev& interior, const double* alpha, double* F,
                      hipStream_t s);
 hipError_t minmax_reset(double* mm, hipStream_t s);

@@ -42,13 +42,13 @@ __device__ __forceinline__ double e_value(const FieldDev& E, int d, const double
       return (s + exp(-t)) / E.c[0];
     }
     case RSFDE_FIELD_POLY_T: {
-      double p = 1.0;
-      for (int i = 0; i < d; ++i) p *= pow(x[i], E.c[3]);
+      double p = 1.0;  // prod_i x_i^c3 (table row AX_E)
+      for (int i = 0; i < d; ++i) p *= E.ax[i][AX_E * Ncl[i] + jc[i]];
       return E.c[0] + E.c[1] * (1.0 + E.c[2] * t) * p;
     }
     case RSFDE_FIELD_SINPROD_COS: {
-      double p = 1.0;
-      for (int i = 0; i < d; ++i) p *= sinpi(x[i]);
+      double p = 1.0;  // prod_i sin(pi x_i) (table row AX_E)
+      for (int i = 0; i < d; ++i) p *= E.ax[i][AX_E * Ncl[i] + jc[i]];
       return E.c[0] + E.c[1] * p * cos(t);
     }
     case RSFDE_FIELD_SINE_FIELD: {
@@ -114,7 +114,7 @@ __device__ __forceinline__ void fields_eval_at(const FieldDev& E, const FieldDev
       double pr[3];
       double u = A;
       for (int i = 0; i < d; ++i) {
-        pr[i] = poly_p(x[i], F.a);
+        pr[i] = F.ax[i][AX_U * Ncl[i] + jc[i]];  // x_i^a (1 - x_i)^a
         u *= pr[i];
       }
       const double ev = e_value(E, d, x, jc, Ncl, t);
@@ -123,13 +123,13 @@ __device__ __forceinline__ void fields_eval_at(const FieldDev& E, const FieldDev
         double other = A;
         for (int l = 0; l < d; ++l)
           if (l != i) other *= pr[l];
-        v -= g.kappa[i] * other * riesz_poly(F.mc + i * RSFDE_MC_STRIDE, F.mc[i * RSFDE_MC_STRIDE + 27], F.a, x[i]);
+        v -= g.kappa[i] * other * F.ax[i][AX_RIESZ * Ncl[i] + jc[i]];
       }
     }
   } else {
     if (F.kind == RSFDE_FIELD_MANUFACTURED) {
       double u = F.c[0];
-      for (int i = 0; i < d; ++i) u *= poly_p(x[i], F.a);
+      for (int i = 0; i < d; ++i) u *= F.ax[i][AX_PSI * Ncl[i] + jc[i]];
       v = u;
     }
   }
@@ -171,6 +171,34 @@ __global__ void k_sintab(int K, int Ncl, double lo, double h, double* tab) {
   if (i >= K * Ncl) return;
   const int k = i / Ncl, j = i - k * Ncl;
   tab[i] = sinpi((double)(k + 1) * (lo + (double)j * h));
+}
+
+__global__ void k_axis_tables(const FieldDev E, const FieldDev F, const FieldDev P, const GridDev g,
+                              int axis, double* __restrict__ tab) {
+  const int Ncl = g.N[axis] + 2;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Ncl) return;
+  const double x = g.lo[axis] + (double)j * g.h[axis];
+  double te = 0.0, tu = 0.0, tr = 0.0, tp = 0.0;
+  if (E.kind == RSFDE_FIELD_POLY_T) te = pow(x, E.c[3]);
+  else if (E.kind == RSFDE_FIELD_SINPROD_COS) te = sinpi(x);
+  if (F.kind == RSFDE_FIELD_MANUFACTURED) {
+    tu = poly_p(x, F.a);
+    const double* mc = F.mc + axis * RSFDE_MC_STRIDE;
+    tr = riesz_poly(mc, mc[27], F.a, x);
+  }
+  if (P.kind == RSFDE_FIELD_MANUFACTURED) tp = poly_p(x, P.a);
+  tab[AX_E * Ncl + j] = te;
+  tab[AX_U * Ncl + j] = tu;
+  tab[AX_RIESZ * Ncl + j] = tr;
+  tab[AX_PSI * Ncl + j] = tp;
+}
+
+hipError_t fields_axis_tables(const FieldDev& e, const FieldDev& f, const FieldDev& psi,
+                              const GridDev& g, int axis, double* tab, hipStream_t s) {
+  const int Ncl = g.N[axis] + 2;
+  hipLaunchKernelGGL(k_axis_tables, dim3((Ncl + 255) / 256), dim3(256), 0, s, e, f, psi, g, axis, tab);
+  return hipGetLastError();
 }
 
 hipError_t fields_sintab(int K, int Ncl, double lo, double h, double* tab, hipStream_t s) {
