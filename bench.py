@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-strang", action="store_true",
+                    help="skip the run with the Strang circulant preconditioner")
     ap.add_argument("--no-two-sided", action="store_true",
                     help="skip the run of the two-sided form (eq. Pls)")
     ap.add_argument("--no-graphs", action="store_true",
@@ -341,6 +343,25 @@ def main():
                             "gmres_iters_per_step": (gt.iters - it0) / K,
                             "rel_diff_vs_one_sided_gpu": diff, "status": gt.status}
         gt.close()
+
+    # ---- the paper's comparison solver: Strang circulant preconditioner (FP64)
+    if not args.no_strang:
+        gs = Stepper(insts, method=R.RSFDE_SPGM)
+        for _ in range(W):
+            gs.step()
+        it0 = gs.iters
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            gs.step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        diff = max(float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+                   for a, b in zip(gs.us, u64))
+        out["strang"] = {"value": K / el, "unit": "time-steps/s", "ms_per_step": 1e3 * el / K,
+                         "gmres_iters_per_step": (gs.iters - it0) / K,
+                         "rel_diff_vs_tau_gpu": diff, "status": gs.status}
+        gs.close()
 
     # ---- FP64 form with graph replay of the Arnoldi steps (no kernel timing)
     if not args.no_graphs:

@@ -76,6 +76,11 @@ extern "C" {
  *               form are stepped one at a time (no batched launches). */
 #define RSFDE_OPGM  0
 #define RSFDE_TPGM  1
+/*   RSFDE_SPGM  the paper's comparison solver (Section 4): GMRES on A u = b (eq. tls)
+ *               left-preconditioned by ebar c(B_alpha) + c(S_alpha), the Strang
+ *               circulants of every factor (c(B)^{1/2} P_c c(B)^{1/2} with P_c of the
+ *               Strang preconditioner); FP64 only, stepped one instance at a time. */
+#define RSFDE_SPGM  2
 
 typedef struct rsfde_ctx* rsfde_handle;
 
@@ -96,8 +101,8 @@ typedef struct {
   int     x0_mode;      /* 0: GMRES starts from u^{(m)}; 1: from zero */
   double  inner_rtol;   /* RSFDE_MIXED: tolerance of each FP32 inner solve (0 -> 1e-5) */
   int     max_outer;    /* RSFDE_MIXED: refinement sweeps allowed per step (0 -> 30) */
-  int     method;       /* RSFDE_OPGM (0) or RSFDE_TPGM; RSFDE_TPGM with RSFDE_MIXED is
-                           RSFDE_E_UNSUPPORTED */
+  int     method;       /* RSFDE_OPGM (0), RSFDE_TPGM or RSFDE_SPGM; the last two with
+                           RSFDE_MIXED are RSFDE_E_UNSUPPORTED */
 } rsfde_params;
 
 /* Per-instance result of one step (summed over the steps of rsfde_solve). */
@@ -215,11 +220,17 @@ int rsfde_apply_prec(rsfde_handle h, int instance, const double* r, double* out)
  *   RSFDE_PREC_BP_INV     (B_alpha P_alpha)^{-1}       g = 1/mu      (as rsfde_apply_prec)
  *   RSFDE_PREC_PHALF_BINV P_alpha^{-1/2} B_alpha^{-1}  g = 1/sqrt(Lambda mu)   (eq. Pls)
  *   RSFDE_PREC_PHALF      P_alpha^{-1/2}               g = sqrt(Lambda / mu)   (eq. Pls)
+ * and, for an instance of the RSFDE_SPGM form only, the Strang circulant solve
+ *   RSFDE_PREC_STRANG     (ebar c(B) + c(S))^{-1} = (1/prod N_l) H diag(1/m) H, with H
+ *                         the separable Hartley transform and m the eigenvalues of
+ *                         ebar c(B) + c(S) (Section 4)
  * r and out: FP64 device vectors of the instance's size, not overlapping; needs ebar.
- * Errors: RSFDE_E_INVALID_ARG (bad form, null pointer), RSFDE_E_STATE, RSFDE_E_HIP. */
+ * Errors: RSFDE_E_INVALID_ARG (bad form, null pointer), RSFDE_E_STATE (ebar not set,
+ * or RSFDE_PREC_STRANG on another form), RSFDE_E_HIP. */
 #define RSFDE_PREC_BP_INV      0
 #define RSFDE_PREC_PHALF_BINV  1
 #define RSFDE_PREC_PHALF       2
+#define RSFDE_PREC_STRANG      3
 int rsfde_apply_prec_form(rsfde_handle h, int instance, int form, const double* r, double* out);
 
 /* out = F = (H_{alpha_d} ... H_{alpha_1}) f restricted to the interior, from f on the

@@ -1,7 +1,8 @@
 """FP64 CPU oracle: quasi-compact Crank-Nicolson scheme for the variable-coefficient
 Riesz space-fractional diffusion equation, solved at every step by GMRES(m) with
 the sine-transform (tau) preconditioner: the one-sided form (eq. one-sided) and
-the two-sided form (eq. Pls).
+the two-sided form (eq. Pls); and, as the paper's comparison solver, GMRES with
+the Strang circulant preconditioner (Section 4).
 
 TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
 cpu_baseline leg of bench.py may import or call this module.  It is written from
@@ -27,6 +28,9 @@ Readings of points the paper leaves open (each also listed in the design notes):
   * Two-sided form: GMRES with no further preconditioner on eq. Pls, started from
     utilde_0 = P^{1/2} u^{(m)} (the image of the one-sided start), with the same
     stopping rule on its own residual; u^{(m+1)} = P^{-1/2} utilde.
+  * Strang form: left preconditioning of eq. tls by c(B) P_c = ebar c(B) + c(S)
+    (the circulant counterpart of B P; c(B)^{1/2} P_c c(B)^{1/2} with commuting
+    circulants), same start and stopping rule as the one-sided form.
 """
 from __future__ import annotations
 
@@ -38,6 +42,7 @@ import numpy as np
 __all__ = [
     "fcd_weights", "fcd_weights_gamma", "toeplitz_dense", "B_dense", "sine_matrix",
     "hankel_dense", "tau_dense", "tau_eigs_cosine", "B_eigs", "riesz_poly_derivative",
+    "strang_first_column", "circulant_dense", "strang_eigs",
     "OracleProblem", "gmres_left", "run",
 ]
 
@@ -143,6 +148,30 @@ def B_eigs(alpha: float, N: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # Section 1: Riesz derivative of the polynomial x^a (1-x)^a on [0,1]
 # ----------------------------------------------------------------------------
+
+# ----------------------------------------------------------------------------
+# Section 4: the Strang circulant s(T) of a symmetric Toeplitz matrix
+# ----------------------------------------------------------------------------
+
+def strang_first_column(t: np.ndarray) -> np.ndarray:
+    """First column of s(T): the central diagonals of T (first column t) copied and
+    wrapped around, c_k = t_k for k <= N/2 and c_k = t_{N-k} above."""
+    N = len(t)
+    return np.array([t[k] if k <= N // 2 else t[N - k] for k in range(N)], dtype=np.float64)
+
+
+def circulant_dense(c: np.ndarray) -> np.ndarray:
+    """The N x N circulant matrix with first column c."""
+    N = len(c)
+    i = np.arange(N)
+    return c[(i[:, None] - i[None, :]) % N]
+
+
+def strang_eigs(t: np.ndarray) -> np.ndarray:
+    """Eigenvalues of s(T) in discrete-Fourier order (mode j at [j]): the DFT of its
+    first column, real because the column is symmetric."""
+    return np.fft.fft(strang_first_column(t)).real
+
 
 def _poly_coeffs(a: int) -> np.ndarray:
     """Coefficients c_k of x^a (1-x)^a = sum_k c_k x^k."""
@@ -436,6 +465,36 @@ class OracleProblem:
         """Atilde = E + B_alpha^{-1} S_alpha (eq. equi)."""
         return e * X + self.apply_B_inv(self.apply_S(X))
 
+    # -- Strang circulant preconditioner (Section 4)
+    def strang_m(self) -> np.ndarray:
+        """Eigenvalues of ebar c(B_alpha) + c(S_alpha) (the Strang circulants of each
+        factor, eqs. Pcir/cirSalpha), in discrete-Fourier order on every axis."""
+        def along(v, i):
+            return v.reshape([-1 if a == self.d - 1 - i else 1 for a in range(self.d)])
+        bB, bS = [], []
+        for i in range(self.d):
+            N, al = self.N[i], self.inst.alpha[i]
+            tb = np.zeros(N)
+            tb[0] = 1.0 - al / 12.0
+            if N > 1:
+                tb[1] = al / 24.0
+            bB.append(strang_eigs(tb))
+            bS.append(strang_eigs(self.s[i]))
+        lamK = np.ones(self.shape)
+        for i in range(self.d):
+            lamK = lamK * along(bB[i], i)
+        m = self.ebar * lamK
+        for i in range(self.d):
+            term = np.ones(self.shape) * self.eta[i]
+            for l in range(self.d):
+                term = term * along(bS[l] if l == i else bB[l], l)
+            m = m + term
+        return m
+
+    def apply_strang_prec_inv(self, R: np.ndarray) -> np.ndarray:
+        """(ebar c(B) + c(S))^{-1} r by the d-dimensional DFT."""
+        return np.real(np.fft.ifftn(np.fft.fftn(R) / self.strang_m()))
+
     def apply_sine(self, X: np.ndarray) -> np.ndarray:
         Y = X
         for i in range(self.d):
@@ -484,6 +543,19 @@ class OracleProblem:
                            max_cycles=self.inst.max_cycles if max_cycles is None else max_cycles)
         return x, st
 
+
+    def step_strang(self, u: np.ndarray, m: int, x0_mode: int = 0, restart: Optional[int] = None,
+                    rtol: Optional[float] = None, max_cycles: Optional[int] = None):
+        """One step of eq. tls by GMRES left-preconditioned with ebar c(B) + c(S)."""
+        th = self.t_half(m)
+        e = self.e_at(th)
+        F = self.F_from_closure(self.f_closure_at(th))
+        b = self.rhs(e, F, u)
+        x0 = u.copy() if x0_mode == 0 else np.zeros_like(u)
+        return gmres_left(lambda v: self.apply_A(e, v), self.apply_strang_prec_inv, b, x0,
+                          restart=self.inst.restart if restart is None else restart,
+                          rtol=self.inst.rtol if rtol is None else rtol,
+                          max_cycles=self.inst.max_cycles if max_cycles is None else max_cycles)
 
     def step_two_sided(self, u: np.ndarray, m: int, x0_mode: int = 0,
                        restart: Optional[int] = None, rtol: Optional[float] = None,
@@ -585,11 +657,12 @@ def gmres_left(apply_A: Callable, apply_Minv: Callable, b: np.ndarray, x0: np.nd
 
 def run(inst, steps: Optional[int] = None, ebar: Optional[float] = None, x0_mode: int = 0,
         u0: Optional[np.ndarray] = None, m0: int = 0, track_error: bool = False,
-        callback: Optional[Callable] = None, two_sided: bool = False) -> Dict:
+        callback: Optional[Callable] = None, two_sided: bool = False, strang: bool = False) -> Dict:
     """Run `steps` Crank-Nicolson steps (default: all M) from u0 (default psi) starting
     at step index m0, each solved in the one-sided form (eq. one-sided) or, with
-    two_sided, in the two-sided form (eq. Pls).  Returns the final u (flat, x_1
-    fastest) and per-step stats."""
+    two_sided, in the two-sided form (eq. Pls), or with strang, with the Strang
+    circulant preconditioner.  Returns the final u (flat, x_1 fastest) and per-step
+    stats."""
     P = OracleProblem(inst, ebar=ebar)
     u = P.psi() if u0 is None else np.asarray(u0, dtype=np.float64).reshape(P.shape).copy()
     steps = inst.M - m0 if steps is None else steps
@@ -598,6 +671,8 @@ def run(inst, steps: Optional[int] = None, ebar: Optional[float] = None, x0_mode
     for m in range(m0, m0 + steps):
         if two_sided:
             u, st = P.step_two_sided(u, m, x0_mode=x0_mode)
+        elif strang:
+            u, st = P.step_strang(u, m, x0_mode=x0_mode)
         else:
             u, st = P.step(u, m, x0_mode=x0_mode)
         iters.append(st["iters"])

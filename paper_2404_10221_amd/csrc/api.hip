@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "dht.h"
 #include "fields.h"
 #include "krylov.h"
 #include "pass.h"
@@ -33,7 +34,12 @@
                                              hipEvent_t, hipEvent_t);                       \
   template <>                                                                                \
   hipError_t launch_spectrum_L<L>(const double*, int, const cpx<double>*, double*, float*,  \
-                                  double*, hipStream_t);
+                                  double*, hipStream_t);                                     \
+  template <>                                                                                \
+  hipError_t launch_dht_L<L>(const DhtArgs&, int64_t, hipStream_t);                          \
+  template <>                                                                                \
+  hipError_t launch_dht_tables_L<L>(int, const cpx<double>*, cpx<double>*, cpx<double>*,     \
+                                    hipStream_t);
 RSFDE_FOR_EACH_L(RSFDE_DECL)
 #undef RSFDE_DECL
 
@@ -89,6 +95,29 @@ static void pass_shape_rt(int L, bool fp32, bool strided, int var, int* nt, int*
   *ppt = 0;
 }
 
+static hipError_t launch_dht(int L, const DhtArgs& a, int64_t nblocks, hipStream_t s) {
+  switch (L) {
+#define RSFDE_CASE(LL) \
+  case LL:             \
+    return launch_dht_L<LL>(a, nblocks, s);
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dht_tables(int L, int N, const cpx<double>* tw64, cpx<double>* chirp,
+                             cpx<double>* khat, hipStream_t st) {
+  switch (L) {
+#define RSFDE_CASE(LL) \
+  case LL:             \
+    return launch_dht_tables_L<LL>(N, tw64, chirp, khat, st);
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_spectrum(int L, const double* s, int N, const cpx<double>* tw64, double* chat64,
                            float* chat32, double* q, hipStream_t st) {
   switch (L) {
@@ -117,6 +146,10 @@ struct Axis {
   float *chat32 = nullptr, *lam32 = nullptr, *wq32 = nullptr;
   cpx<double>* tw64 = nullptr;
   cpx<float>* tw32 = nullptr;
+  // Strang circulant form only: chirp (N), Bluestein kernel spectrum (L), Strang
+  // eigenvalues of B and eta sigma / b (N each, Fourier order)
+  cpx<double>*chirp = nullptr, *khat = nullptr;
+  double *slam = nullptr, *swq = nullptr;
 };
 
 struct FieldHost {
@@ -319,8 +352,9 @@ static int validate(const rsfde_params* p) {
   if (p->x0_mode != 0 && p->x0_mode != 1) return RSFDE_E_INVALID_ARG;
   if (!(p->inner_rtol >= 0.0 && p->inner_rtol < 1.0)) return RSFDE_E_INVALID_ARG;
   if (p->max_outer < 0) return RSFDE_E_INVALID_ARG;
-  if (p->method != RSFDE_OPGM && p->method != RSFDE_TPGM) return RSFDE_E_INVALID_ARG;
-  if (p->method == RSFDE_TPGM && p->precision != RSFDE_FP64) return RSFDE_E_UNSUPPORTED;
+  if (p->method != RSFDE_OPGM && p->method != RSFDE_TPGM && p->method != RSFDE_SPGM)
+    return RSFDE_E_INVALID_ARG;
+  if (p->method != RSFDE_OPGM && p->precision != RSFDE_FP64) return RSFDE_E_UNSUPPORTED;
   if (n > ((int64_t)1 << 34)) return RSFDE_E_INVALID_ARG;
   for (int i = 0; i < p->d; ++i) {
     const int64_t L = 2 * (p->n[i] + 1);
@@ -371,6 +405,12 @@ static void layout(Inst& I, Bump& B) {
     A.chat32 = B.take<float>(A.L);
     A.tw64 = B.take<cpx<double>>(A.L);
     A.tw32 = B.take<cpx<float>>(A.L);
+    if (p.method == RSFDE_SPGM) {
+      A.chirp = B.take<cpx<double>>(A.N);
+      A.khat = B.take<cpx<double>>(A.L);
+      A.slam = B.take<double>(A.N);
+      A.swq = B.take<double>(A.N);
+    }
   }
   I.e = B.take<double>(I.n);
   if (p.precision == RSFDE_MIXED) I.e32 = B.take<float>(I.n);
@@ -544,6 +584,87 @@ static int run_prec(rsfde_ctx* h, const Inst& I, bool fp32, const double* r, dou
   return RSFDE_OK;
 }
 
+// (ebar c(B) + c(S))^{-1} r of the Strang circulant form: Hartley passes along
+// axes d-1..1, Hartley / 1/m / Hartley along axis 0, Hartley along axes 1..d-1.
+// r is the temporary T[ri] (or any FP64 vector with ri = -1); the passes use the
+// temporaries after it in turn, and the last one writes out.
+static int run_strang_prec(rsfde_ctx* h, const Inst& I, const double* r, int ri, double* out,
+                           const int* stop_fl = nullptr) {
+  const int d = I.d;
+  void* const* T = I.tmp;
+  double pscale = 1.0;
+  for (int l = 0; l < d; ++l) pscale /= (double)I.ax[l].N;
+  auto mk = [&](int axis, int op) {
+    DhtArgs a;
+    memset(&a, 0, sizeof(a));
+    const Axis& A = I.ax[axis];
+    a.op = op;
+    a.N = A.N;
+    a.d = d;
+    a.axis = axis;
+    int64_t inner = 1;
+    for (int l = 0; l < axis; ++l) inner *= I.ax[l].N;
+    a.inner = inner;
+    a.npencil = I.n / A.N;
+    a.npairs = (a.npencil + 1) / 2;
+    a.xcd_remap = axis > 0 ? 1 : 0;
+    a.chirp = A.chirp;
+    a.khat = A.khat;
+    a.tw = A.tw64;
+    for (int l = 0; l < 3; ++l) {
+      a.Nax[l] = l < d ? I.ax[l].N : 1;
+      a.lam[l] = l < d ? I.ax[l].slam : nullptr;
+      a.wq[l] = l < d ? I.ax[l].swq : nullptr;
+    }
+    a.ebar = I.ebar;
+    a.pscale = pscale;
+    a.stop_fl = stop_fl;
+    return a;
+  };
+  auto launch = [&](const DhtArgs& a, const void* in, double* o) -> int {
+    DhtArgs b = a;
+    b.in = (const double*)in;
+    b.out = o;
+    const int64_t nb = b.xcd_remap ? (b.npairs + 7) / 8 * 8 : b.npairs;
+    if (nb > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
+    const int L = I.ax[b.axis].L;
+    return timed_launch(h, b.op == DHT_SCALE ? RSFDE_K_DSD : RSFDE_K_DST, 16.0 * (double)I.n,
+                        [&](hipEvent_t ea, hipEvent_t eb) -> hipError_t {
+                          if (ea) {
+                            hipError_t e = hipEventRecord(ea, h->stream);
+                            if (e != hipSuccess) return e;
+                          }
+                          hipError_t e = launch_dht(L, b, nb, h->stream);
+                          if (e == hipSuccess && eb) e = hipEventRecord(eb, h->stream);
+                          return e;
+                        });
+  };
+  if (d == 1) return launch(mk(0, DHT_SCALE), r, out);
+  int cur = ri;
+  const void* src = r;
+  auto next = [&]() { return cur < 0 ? 0 : (cur + 1) & 3; };
+  for (int ax = d - 1; ax >= 1; --ax) {
+    const int o = next();
+    CKS(launch(mk(ax, DHT_PLAIN), src, (double*)T[o]));
+    cur = o;
+    src = T[o];
+  }
+  {
+    const int o = next();
+    CKS(launch(mk(0, DHT_SCALE), src, (double*)T[o]));
+    cur = o;
+    src = T[o];
+  }
+  for (int ax = 1; ax <= d - 1; ++ax) {
+    const bool last = ax == d - 1;
+    const int o = next();
+    CKS(launch(mk(ax, DHT_PLAIN), src, last ? out : (double*)T[o]));
+    cur = o;
+    src = T[o];
+  }
+  return RSFDE_OK;
+}
+
 enum Chain { CH_APPLY_A = 0, CH_RHS = 1, CH_RESID = 2, CH_OPER = 3 };
 
 // Operator chains along the axes (x_1 first).  CH_APPLY_A: out = A x.
@@ -557,7 +678,12 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
                      const GmRes* gm = nullptr, const int* stop_fl = nullptr) {
   const int d = I.d;
   const void* e = fp32 ? (const void*)I.e32 : (const void*)I.ecur;
-  const bool prec = kind == CH_RESID || kind == CH_OPER;
+  const bool strang = I.p.method == RSFDE_SPGM && (kind == CH_RESID || kind == CH_OPER);
+  // the tau preconditioner fused into the operator passes (not in the Strang form,
+  // whose solve follows the operator as its own chain from a temporary)
+  const bool prec = (kind == CH_RESID || kind == CH_OPER) && !strang;
+  const int st_i = d == 3 ? 0 : 3;  // Strang form: temporary between the two chains
+  double* const op_out = strang ? (double*)I.tmp[st_i] : out;
   const bool two = I.p.method == RSFDE_TPGM;
   const int pm = two ? PM_PH_BINV : PM_BP_INV;
   if (two && kind == CH_OPER) {
@@ -579,13 +705,15 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
     a.gam = kind == CH_RESID ? -1.0 : 1.0;
     a.in_x = xin;
     a.xcoef = xcoef;
-    a.out_a = out;
+    a.out_a = op_out;
     if (gm) {
       a.use_gm = 1;
       a.gm = *gm;
       a.sc_ptr = nullptr;
     }
-    return run_pass(h, I, a, fp32);
+    CKS(run_pass(h, I, a, fp32));
+    if (strang) return run_strang_prec(h, I, op_out, st_i, out, stop_fl);
+    return RSFDE_OK;
   }
   // first axis
   PassArgs a = mk_pass(I, 0, OP_MV_FIRST, fp32);
@@ -625,8 +753,10 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
   z.stop_fl = stop_fl;
   if (!prec) {
     z.flags = FL_OUT64;
-    z.out_a = out;
-    return run_pass(h, I, z, fp32);
+    z.out_a = op_out;
+    CKS(run_pass(h, I, z, fp32));
+    if (strang) return run_strang_prec(h, I, op_out, st_i, out, stop_fl);
+    return RSFDE_OK;
   }
   z.flags = FL_DST_AFTER;
   int cur = d == 2 ? 2 : 0;  // holds the transformed w
@@ -1536,6 +1666,9 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
       pscale /= (double)A.L;
       hipError_t e = setup_axis_tables(A.alpha, A.N, A.L, A.eta, A.s, A.tw64, A.tw32, A.chat64,
                                        A.chat32, A.q, A.lam64, A.lam32, A.wq64, A.wq32, h->stream);
+      if (e == hipSuccess && I.p.method == RSFDE_SPGM)
+        e = setup_strang_tables(A.L, A.alpha, A.N, A.eta, A.s, A.tw64, A.chirp, A.khat, A.slam,
+                                A.swq, h->stream);
       if (e != hipSuccess) {
         g_last_hip = e;
         status = RSFDE_E_HIP;
@@ -1921,10 +2054,15 @@ int rsfde_apply_prec(rsfde_handle h, int instance, const double* r, double* out)
 
 int rsfde_apply_prec_form(rsfde_handle h, int instance, int form, const double* r, double* out) {
   if (!h || instance < 0 || instance >= h->count || !r || !out) return RSFDE_E_INVALID_ARG;
-  if (form != RSFDE_PREC_BP_INV && form != RSFDE_PREC_PHALF_BINV && form != RSFDE_PREC_PHALF)
+  if (form != RSFDE_PREC_BP_INV && form != RSFDE_PREC_PHALF_BINV && form != RSFDE_PREC_PHALF &&
+      form != RSFDE_PREC_STRANG)
     return RSFDE_E_INVALID_ARG;
   Inst& I = h->inst[instance];
   if (!I.ebar_set) return RSFDE_E_STATE;
+  if (form == RSFDE_PREC_STRANG) {
+    if (I.p.method != RSFDE_SPGM) return RSFDE_E_STATE;  // its tables exist in that form only
+    return run_strang_prec(h, I, r, -1, out);
+  }
   const int pm = form == RSFDE_PREC_BP_INV ? PM_BP_INV : (form == RSFDE_PREC_PHALF_BINV ? PM_PH_BINV : PM_PH);
   return run_prec(h, I, false, r, out, pm);
 }

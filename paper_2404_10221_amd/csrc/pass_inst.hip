@@ -1,6 +1,7 @@
 // One instantiation unit of the pencil pass kernels and the setup spectrum
 // kernel; compiled once per transform length with -DRSFDE_PASS_L=<L> so the
 // lengths build in parallel.
+#include "dht.h"
 #include "pass.h"
 #include "setup.h"
 
@@ -10,6 +11,7 @@
 
 RSFDE_INSTANTIATE_PASS(double, RSFDE_PASS_L)
 RSFDE_INSTANTIATE_PASS(float, RSFDE_PASS_L)
+RSFDE_INSTANTIATE_DHT(RSFDE_PASS_L)
 
 // Spectrum of the circulant embedding c = [t_0..t_{N-1}, 0, 0, 0, t_{N-1}..t_1]
 // (length L = 2(N+1)) of the symmetric Toeplitz factor: FFT(c) is real and even,

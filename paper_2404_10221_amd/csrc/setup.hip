@@ -57,6 +57,31 @@ __global__ void k_lam_wq(double alpha, int N, double eta, const double* __restri
   wq32[i] = (float)w;
 }
 
+__global__ void __launch_bounds__(256)
+k_strang_eigs(int N, double alpha, double eta, const double* __restrict__ s, double* __restrict__ lam,
+              double* __restrict__ wq) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double sig = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double c = k <= N / 2 ? s[k] : s[N - k];
+    const long long r = ((long long)j * k) % N;  // angle 2 pi jk/N reduced mod 2 pi
+    sig += c * cospi(2.0 * (double)r / (double)N);
+  }
+  const double b = (1.0 - alpha / 12.0) + alpha / 12.0 * cospi(2.0 * (double)j / (double)N);
+  lam[j] = b;
+  wq[j] = eta * sig / b;
+}
+
+hipError_t setup_strang_tables(int L, double alpha, int N, double eta, const double* s,
+                               const cpx<double>* tw64, cpx<double>* chirp, cpx<double>* khat,
+                               double* lam, double* wq, hipStream_t st) {
+  hipLaunchKernelGGL(k_strang_eigs, dim3((N + 255) / 256), dim3(256), 0, st, N, alpha, eta, s, lam, wq);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_dht_tables(L, N, tw64, chirp, khat, st);
+}
+
 hipError_t setup_axis_tables(double alpha, int N, int L, double eta, double* s, cpx<double>* tw64,
                              cpx<float>* tw32, double* chat64, float* chat32, double* q,
                              double* lam64, float* lam32, double* wq64, float* wq32,

@@ -26,8 +26,8 @@ RSFDE_E_STATE = -6
 
 RSFDE_FP64 = 0
 RSFDE_MIXED = 1
-RSFDE_OPGM, RSFDE_TPGM = 0, 1
-PREC_BP_INV, PREC_PHALF_BINV, PREC_PHALF = 0, 1, 2
+RSFDE_OPGM, RSFDE_TPGM, RSFDE_SPGM = 0, 1, 2
+PREC_BP_INV, PREC_PHALF_BINV, PREC_PHALF, PREC_STRANG = 0, 1, 2, 3
 
 FIELD_KINDS = {
     "zero": 0, "const": 1, "sumsq_exp": 2, "poly_t": 3, "sinprod_cos": 4,
@@ -261,7 +261,7 @@ def rsfde_apply_prec(h, instance: int, r, out) -> None:
 
 
 def rsfde_apply_prec_form(h, instance: int, form: int, r, out) -> None:
-    """form: PREC_BP_INV, PREC_PHALF_BINV or PREC_PHALF."""
+    """form: PREC_BP_INV, PREC_PHALF_BINV, PREC_PHALF or (Strang-form instances) PREC_STRANG."""
     _check(load_library().rsfde_apply_prec_form(h, instance, form, _ptr(r), _ptr(out)),
            "rsfde_apply_prec_form")
 

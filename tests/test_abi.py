@@ -63,7 +63,8 @@ def _base(**over):
     (dict(max_cycles=0), R.RSFDE_E_INVALID_ARG),
     (dict(precision=2), R.RSFDE_E_INVALID_ARG),
     (dict(x0_mode=3), R.RSFDE_E_INVALID_ARG),
-    (dict(method=2), R.RSFDE_E_INVALID_ARG),
+    (dict(method=3), R.RSFDE_E_INVALID_ARG),
+    (dict(method=R.RSFDE_SPGM, precision=R.RSFDE_MIXED), R.RSFDE_E_UNSUPPORTED),
     (dict(method=R.RSFDE_TPGM, precision=R.RSFDE_MIXED), R.RSFDE_E_UNSUPPORTED),
     (dict(lo=(0.0, 1.0), hi=(1.0, 1.0)), R.RSFDE_E_INVALID_ARG),
     (dict(n=(14, 15)), R.RSFDE_E_UNSUPPORTED),      # 2(N+1) = 30 is not 2^p or 3*2^p

@@ -102,6 +102,14 @@ def test_graph_replay_two_sided(name, grid):
     _same(a, b)
 
 
+def test_graph_replay_strang():
+    # the Strang-circulant form's steps end with the Hartley passes
+    inst = replace(with_grid(config("C2"), (47, 31), M=3), restart=5, max_cycles=60)
+    a = _run([inst], graphs=True, method=R.RSFDE_SPGM)
+    b = _run([inst], graphs=False, method=R.RSFDE_SPGM)
+    _same(a, b)
+
+
 def test_graph_replay_restarts():
     # GMRES(3): several cycles per step, with and without a pending resolve
     inst = replace(with_grid(config("C2"), (47, 47), M=3), restart=3, max_cycles=60)

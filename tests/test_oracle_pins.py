@@ -439,6 +439,75 @@ def test_T11b_tables_2_3_4_two_sided_iterations():
         assert abs(it - it_ref) <= tol, (args, it, it_ref)
 
 
+# --- the Strang circulant preconditioner (Section 4, the comparison solver) ---------
+
+@pytest.mark.parametrize("N", [5, 8, 15, 31])
+def test_T15a_strang_circulant_definition_and_eigenvalues(N):
+    alpha = 1.4
+    t = O.fcd_weights(alpha, N)
+    C = O.circulant_dense(O.strang_first_column(t))
+    T = O.toeplitz_dense(t)
+    # s(T) keeps the central diagonals of T (|i - j| <= N/2) and is symmetric
+    i = np.arange(N)
+    near = np.abs(i[:, None] - i[None, :]) <= N // 2
+    np.testing.assert_array_equal(C[near], T[near])
+    np.testing.assert_array_equal(C, C.T)
+    # its eigenvalues (Fourier order) against a dense symmetric eigensolver
+    np.testing.assert_allclose(np.sort(O.strang_eigs(t)), np.linalg.eigvalsh(C), atol=1e-13)
+    # the tridiagonal B: closed form 1 - alpha/12 + (alpha/12) cos(2 pi j / N)
+    tb = np.zeros(N)
+    tb[0], tb[1] = 1 - alpha / 12, alpha / 24
+    j = np.arange(N)
+    np.testing.assert_allclose(O.strang_eigs(tb), 1 - alpha / 12 + alpha / 12 * np.cos(2 * np.pi * j / N),
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("d,n,alpha,kappa", [
+    (1, (11,), (1.6,), (1.0,)),
+    (2, (7, 6), (1.3, 1.7), (1.0, 0.5)),
+    (3, (5, 4, 3), (1.2, 1.5, 1.8), (1.0, 0.8, 0.6)),
+])
+def test_T15b_strang_solve_equals_dense_circulant_preconditioner(d, n, alpha, kappa):
+    # ebar c(B) + c(S) assembled from dense circulants by Kronecker products
+    P = _problem(d, n, alpha, kappa)
+    sB = []
+    sS = []
+    for i in range(d):
+        tb = np.zeros(P.N[i])
+        tb[0] = 1 - alpha[i] / 12
+        tb[1] = alpha[i] / 24
+        sB.append(O.circulant_dense(O.strang_first_column(tb)))
+        sS.append(O.circulant_dense(O.strang_first_column(P.s[i])))
+    Mc = P.ebar * P.dense_kron(sB)
+    for i in range(d):
+        Mc += P.eta[i] * P.dense_kron([sS[l] if l == i else sB[l] for l in range(d)])
+    r = np.random.default_rng(21).standard_normal(P.shape)
+    z = P.apply_strang_prec_inv(r).ravel()
+    np.testing.assert_allclose(Mc @ z, r.ravel(), rtol=1e-12, atol=1e-12)
+
+
+def _run_example_strang(args):
+    d, alpha, M, Np1 = args
+    return O.run(paper_example(d, alpha, Np1, M), strang=True)["mean_iters"]
+
+
+def test_T15c_table_2_strang_iterations_and_the_two_dimensional_contrast():
+    """SPGM Iter column of Table 2 to within 0.35.  In two dimensions the printed
+    SPGM counts are not reproduced (Table 3, N+1 = 16: 13.0 / 13.9 / 15.4 here against
+    18.4 / 19.0 / 21.0, and they grow more slowly with N), so only the contrast the
+    paper draws is checked: the Strang preconditioner needs far more iterations than
+    the tau preconditioner, and no fewer on the finer grid."""
+    cases = [((1, (a,), int(M), int(Np1)), it) for a, M, Np1, it in _rows("table2_example1_spgm_iter.txt")]
+    two_d = [(2, (1.1, 1.3), 256, 16), (2, (1.1, 1.3), 256, 32)]
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(_run_example_strang, [c[0] for c in cases] + two_d))
+    for (args, it_ref), it in zip(cases, results):
+        assert abs(it - it_ref) <= 0.35, (args, it, it_ref)
+    s16, s32 = results[len(cases):]
+    o16, o32 = [O.run(paper_example(2, (1.1, 1.3), np1, 256))["mean_iters"] for np1 in (16, 32)]
+    assert s16 > o16 + 3.0 and s32 > o32 + 3.0 and s32 >= s16, (s16, s32, o16, o32)
+
+
 def test_T14_fourth_order_in_space():
     # With M tied to N^2 (Section 4), halving h should divide the error by about 16.
     errs = []
