@@ -219,6 +219,50 @@ def test_T7_spectrum_in_theorem_disk(d, n):
     assert np.max(np.abs(lam - 1.0)) <= rho + 1e-12
 
 
+# --- spectral diagnostics of Figs. I-III (Section 4) and Theorem GMRES -------------
+
+def _dense_P_half_inv(P):
+    """P^{-1/2} assembled densely (eigh of B and of P), independent of the sine formulas."""
+    Bk = P.dense_kron(P.B)
+    Bmh = _dense_fn(Bk, lambda w: w ** -0.5)
+    Pd = P.ebar * np.eye(Bk.shape[0]) + Bmh @ (P.dense_BP() - P.ebar * Bk) @ Bmh
+    return _dense_fn(Pd, lambda w: w ** -0.5), Pd, Bk
+
+
+@pytest.mark.parametrize("d,alpha,Np1", [(1, (1.5,), 16), (2, (1.5, 1.7), 16), (3, (1.3, 1.5, 1.7), 8)])
+def test_T8_figures_spectra_and_numerical_range(d, alpha, Np1):
+    """Figs. I-III: at the printed grid sizes (M = 2^12 or 2^10), the eigenvalues of
+    Atilde spread widely while those of P^{-1} Atilde cluster at 1, and P^{-1} Atilde
+    and P^{-1/2} Atilde P^{-1/2} share their spectrum.  Theorem GMRES: the numerical
+    range of P^{-1/2} Atilde P^{-1/2} lies in the disk around 1 of radius
+    rho = max((e_hat - e_check)/(e_hat + e_check), sqrt(6)/4); checked rigorously
+    through support lines at K angles (W lies in the K-gon they bound, whose
+    circumradius about 1 is at most the largest support value / cos(pi/K))."""
+    M = 4096 if d < 3 else 1024
+    inst = paper_example(d, alpha, Np1, M)
+    P = O.OracleProblem(inst)
+    Ph, Pd, Bk = _dense_P_half_inv(P)
+    e = P.e_at(P.t_half(M - 1))
+    At = np.diag(e.ravel()) + np.linalg.solve(Bk, P.dense_A(e) - Bk @ np.diag(e.ravel()))
+    lam_A = np.linalg.eigvals(At)
+    lam_P = np.linalg.eigvals(np.linalg.solve(Pd, At))
+    lam_2 = np.linalg.eigvals(Ph @ At @ Ph)
+    np.testing.assert_allclose(np.sort_complex(lam_P), np.sort_complex(lam_2), rtol=1e-9, atol=1e-9)
+    spread = lambda z: np.abs(z).max() / np.abs(z).min()
+    assert spread(lam_A) > 10 * spread(lam_P), (spread(lam_A), spread(lam_P))
+    ehat, echk = -np.inf, np.inf
+    for m in range(M):
+        em = P.e_at(P.t_half(m))
+        ehat, echk = max(ehat, em.max()), min(echk, em.min())
+    rho = max((ehat - echk) / (ehat + echk), math.sqrt(6) / 4)
+    X = Ph @ At @ Ph - np.eye(At.shape[0])
+    K = 360
+    sup = max(np.linalg.eigvalsh(0.5 * (np.exp(1j * th) * X + np.exp(-1j * th) * X.conj().T)).max()
+              for th in 2 * np.pi * np.arange(K) / K)
+    assert sup / math.cos(math.pi / K) <= rho, (sup, rho)
+    assert np.abs(lam_P - 1).max() <= rho
+
+
 def test_T12_alpha_two_constant_e_converges_in_one_iteration():
     # alpha = 2: s = (2, -1, 0, ...), S is tridiagonal so tau(S) = S; with constant e = ebar
     # the preconditioner B P equals A and GMRES needs exactly one iteration.
