@@ -101,10 +101,25 @@ __device__ __forceinline__ void set_comp(cpx<R>& z, int c, R v) {
 // Variant VAR halves F VAR times; the host picks a variant per axis by timing
 // them at setup (the tile autotuner).
 #define RSFDE_PASS_VARIANTS 3
+
+// Pitch (in elements) of the F sequences of a workgroup.  In a strided tile the
+// lanes of a wavefront cover 2F pencils at consecutive positions, i.e. the same
+// positions of F sequences; starting consecutive sequences 256/F bytes apart
+// modulo 256 gives those F x (positions) accesses one bank each.
+template <typename R, int L, int F>
+struct LdsPitch {
+  static constexpr int S = LdsSeq<R, L>::size;
+  static constexpr int EB = (int)sizeof(cpx<R>);
+  static constexpr int M = 256 / EB;  // elements per 256 bytes
+  static constexpr int want = F == 1 ? 0 : ((256 / F) / EB > 1 ? (256 / F) / EB : 1);
+  static constexpr int value = S + ((want - S % M) % M + M) % M;
+};
+
 template <typename R, int L, bool STRIDED, int VAR>
 struct PassShape {
   static constexpr int T = FftPlan<L>::T;
-  static constexpr int bytes_per_fft = (LdsSeq<R, L>::size + 4) * (int)sizeof(cpx<R>);
+  // (sized for the largest pitch, S + M - 1)
+  static constexpr int bytes_per_fft = (LdsSeq<R, L>::size + LdsPitch<R, L, 1>::M) * (int)sizeof(cpx<R>);
   // LDS left for the transforms: 160 KB minus the twiddle table, the circulant spectrum
   // and 2 KB for the small shared arrays (block sums, Givens column, y)
   static constexpr int cap =
@@ -124,8 +139,7 @@ template <typename R, int L, int F, bool STRIDED>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) {
   using P = FftPlan<L>;
   constexpr int T = P::T, E = P::E, NT = F * T, PT = 2 * F;
-  // sequences 64 bytes apart modulo 256 (strided tiles spread over the banks)
-  constexpr int LP = LdsSeq<R, L>::size + 4;
+  constexpr int LP = LdsPitch<R, L, F>::value;
   constexpr int NE = STRIDED ? E : E / 2;  // element slots per thread
   __shared__ cpx<R> lds[F * LP];
   __shared__ cpx<R> twl[TwHalf<R, L>::size];
