@@ -21,7 +21,11 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 }
 
 // threads per block for a sweep handling up to KM basis vectors
-template <int KM> struct SweepNT { static constexpr int value = KM <= 8 ? 1024 : (KM <= 16 ? 512 : 256); };
+// (sweep 2 keeps up to 16 basis values per element in registers for its dots)
+template <int W, int KM> struct SweepNT {
+  static constexpr int value = W == 2 ? (KM <= 8 ? 1024 : (KM <= 16 ? 512 : 256))
+                                      : (KM <= 16 ? 1024 : (KM <= 32 ? 512 : 256));
+};
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
@@ -166,7 +170,7 @@ __device__ __forceinline__ void ld_cols(T (&v)[C], const T* __restrict__ V, int6
 // ---- CGS2 sweep 1: partials of Vbar^T w ---------------------------------------------------
 template <int KM>
 __device__ __forceinline__ void sweep1_body(const KryArgs& a, int bid, int nblk) {
-  constexpr int NT = SweepNT<KM>::value;
+  constexpr int NT = SweepNT<1, KM>::value;
   constexpr int CH = KM < 8 ? KM : 8;
   if (a.st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
@@ -210,7 +214,7 @@ __device__ __forceinline__ void sweep1_body(const KryArgs& a, int bid, int nblk)
 }
 
 template <int KM>
-__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep1(const KryArgs a) {
+__global__ void __launch_bounds__((SweepNT<1, KM>::value)) k_sweep1(const KryArgs a) {
   sweep1_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
@@ -242,7 +246,7 @@ __device__ __forceinline__ void sub_cols(T& wi, T (&vk)[KEEP ? KM : 1], const T*
 // ---- CGS2 sweep 2: h = Vbar^T w / |v| ; w -= V h ; partials of Vbar^T w ------------------
 template <int KM>
 __device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk) {
-  constexpr int NT = SweepNT<KM>::value;
+  constexpr int NT = SweepNT<2, KM>::value;
   constexpr int CH = KM < 8 ? KM : 8;
   constexpr bool KEEP = KM <= 16;  // basis values kept in registers for the dots
   GmresState* st = a.st;
@@ -308,14 +312,14 @@ __device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk)
 }
 
 template <int KM>
-__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep2(const KryArgs a) {
+__global__ void __launch_bounds__((SweepNT<2, KM>::value)) k_sweep2(const KryArgs a) {
   sweep2_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
 // ---- CGS2 sweep 3: h2 = Vbar^T w / |v| ; w -= V h2 ; partials of ||w||^2 -----------------
 template <int KM>
 __device__ __forceinline__ void sweep3_body(const KryArgs& a, int bid, int nblk) {
-  constexpr int NT = SweepNT<KM>::value;
+  constexpr int NT = SweepNT<3, KM>::value;
   GmresState* st = a.st;
   if (st->FL[a.j] != GM_RUNNING) return;
   const int nv = a.j + 1;
@@ -356,7 +360,7 @@ __device__ __forceinline__ void sweep3_body(const KryArgs& a, int bid, int nblk)
 }
 
 template <int KM>
-__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep3(const KryArgs a) {
+__global__ void __launch_bounds__((SweepNT<3, KM>::value)) k_sweep3(const KryArgs a) {
   sweep3_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
@@ -453,20 +457,20 @@ hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial
   return hipGetLastError();
 }
 
-#define KRY_SWEEP(KERNEL, nv, g, a, s)                                                          \
+#define KRY_SWEEP(KERNEL, W, nv, g, a, s)                                                       \
   do {                                                                                          \
-    if ((nv) <= 8) hipExtLaunchKernelGGL(KERNEL<8>, g, dim3(SweepNT<8>::value), 0, s, ea, eb, 0, a); \
-    else if ((nv) <= 16) hipExtLaunchKernelGGL(KERNEL<16>, g, dim3(SweepNT<16>::value), 0, s, ea, eb, 0, a); \
-    else if ((nv) <= 32) hipExtLaunchKernelGGL(KERNEL<32>, g, dim3(SweepNT<32>::value), 0, s, ea, eb, 0, a); \
-    else hipExtLaunchKernelGGL(KERNEL<64>, g, dim3(SweepNT<64>::value), 0, s, ea, eb, 0, a);    \
+    if ((nv) <= 8) hipExtLaunchKernelGGL(KERNEL<8>, g, dim3(SweepNT<W, 8>::value), 0, s, ea, eb, 0, a); \
+    else if ((nv) <= 16) hipExtLaunchKernelGGL(KERNEL<16>, g, dim3(SweepNT<W, 16>::value), 0, s, ea, eb, 0, a); \
+    else if ((nv) <= 32) hipExtLaunchKernelGGL(KERNEL<32>, g, dim3(SweepNT<W, 32>::value), 0, s, ea, eb, 0, a); \
+    else hipExtLaunchKernelGGL(KERNEL<64>, g, dim3(SweepNT<W, 64>::value), 0, s, ea, eb, 0, a);    \
   } while (0)
 
 hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
   const int nv = a.j + 1;
   const dim3 g(kry_blocks(a.n));
-  if (which == 1) KRY_SWEEP(k_sweep1, nv, g, a, s);
-  else if (which == 2) KRY_SWEEP(k_sweep2, nv, g, a, s);
-  else KRY_SWEEP(k_sweep3, nv, g, a, s);
+  if (which == 1) KRY_SWEEP(k_sweep1, 1, nv, g, a, s);
+  else if (which == 2) KRY_SWEEP(k_sweep2, 2, nv, g, a, s);
+  else KRY_SWEEP(k_sweep3, 3, nv, g, a, s);
   return hipGetLastError();
 }
 
@@ -486,7 +490,7 @@ __device__ __forceinline__ KryArgs kb_args(const KBatch& d, int j) {
 }
 
 template <int W, int KM>
-__global__ void __launch_bounds__(SweepNT<KM>::value) k_sweep_b(const KLaunch kl) {
+__global__ void __launch_bounds__((SweepNT<W, KM>::value)) k_sweep_b(const KLaunch kl) {
   const int slot = batch_slot(kl.start, kl.ninst, blockIdx.x);
   const KBatch& d = kl.desc[slot];
   const KryArgs a = kb_args(d, kl.j);
@@ -523,10 +527,10 @@ __global__ void __launch_bounds__(256) k_cycle_init_fin_b(const KLaunch kl) {
 
 #define KRY_SWEEP_B(W, nv, g, kl, s)                                                              \
   do {                                                                                            \
-    if ((nv) <= 8) hipExtLaunchKernelGGL((k_sweep_b<W, 8>), g, dim3(SweepNT<8>::value), 0, s, ea, eb, 0, kl); \
-    else if ((nv) <= 16) hipExtLaunchKernelGGL((k_sweep_b<W, 16>), g, dim3(SweepNT<16>::value), 0, s, ea, eb, 0, kl); \
-    else if ((nv) <= 32) hipExtLaunchKernelGGL((k_sweep_b<W, 32>), g, dim3(SweepNT<32>::value), 0, s, ea, eb, 0, kl); \
-    else hipExtLaunchKernelGGL((k_sweep_b<W, 64>), g, dim3(SweepNT<64>::value), 0, s, ea, eb, 0, kl); \
+    if ((nv) <= 8) hipExtLaunchKernelGGL((k_sweep_b<W, 8>), g, dim3(SweepNT<W, 8>::value), 0, s, ea, eb, 0, kl); \
+    else if ((nv) <= 16) hipExtLaunchKernelGGL((k_sweep_b<W, 16>), g, dim3(SweepNT<W, 16>::value), 0, s, ea, eb, 0, kl); \
+    else if ((nv) <= 32) hipExtLaunchKernelGGL((k_sweep_b<W, 32>), g, dim3(SweepNT<W, 32>::value), 0, s, ea, eb, 0, kl); \
+    else hipExtLaunchKernelGGL((k_sweep_b<W, 64>), g, dim3(SweepNT<W, 64>::value), 0, s, ea, eb, 0, kl); \
   } while (0)
 
 hipError_t kry_sweep_batched(int which, const KLaunch& kl, int64_t nblocks, hipStream_t s,
