@@ -232,6 +232,36 @@ __device__ __forceinline__ void dft(cpx<R>* v) {
   else static_assert(RAD == 2, "unsupported radix");
 }
 
+// Twiddles w[r] = W^{r m} (conjugated for DIR = +1), r = 1..RAD-1, of one butterfly:
+// the table values at r = 1, 2, 4 (and 8, 12 for RAD = 16) and products of two of
+// them for the rest.  Three LDS reads instead of seven for radix 8, five instead of
+// fifteen for radix 16; every power is at most two roundings from exact.
+template <typename R, int RAD, int DIR, int S, typename TW>
+__device__ __forceinline__ void tw_powers(const TW& tw, int m, cpx<R>* w) {
+  static_assert(RAD == 2 || RAD == 3 || RAD == 4 || RAD == 8 || RAD == 16, "unsupported radix");
+  auto rd = [&](int mm) {
+    cpx<R> x = tw.template get<S>(0, 0, mm);
+    if (DIR > 0) x.y = -x.y;
+    return x;
+  };
+  w[1] = rd(m);
+  if constexpr (RAD >= 3) w[2] = rd(2 * m);
+  if constexpr (RAD >= 4) w[3] = cmul(w[2], w[1]);
+  if constexpr (RAD >= 8) {
+    w[4] = rd(4 * m);
+#pragma unroll
+    for (int r = 5; r < 8; ++r) w[r] = cmul(w[4], w[r - 4]);
+  }
+  if constexpr (RAD == 16) {
+    w[8] = rd(8 * m);
+    w[12] = rd(12 * m);
+#pragma unroll
+    for (int r = 9; r < 12; ++r) w[r] = cmul(w[8], w[r - 8]);
+#pragma unroll
+    for (int r = 13; r < 16; ++r) w[r] = cmul(w[12], w[r - 12]);
+  }
+}
+
 // One Stockham stage on the thread's part of one transform held in LDS;
 // twl is the LDS twiddle table filled by twiddle_fill.
 template <typename R, int L, int DIR, int S, typename TW>
@@ -266,12 +296,10 @@ __device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const T
     if constexpr (Ns > 1) {
       const int k = j % Ns;
       constexpr int step = L / (Ns * RAD);
+      cpx<R> w[RAD];
+      tw_powers<R, RAD, DIR, S>(tw, k * step, w);
 #pragma unroll
-      for (int r = 1; r < RAD; ++r) {
-        cpx<R> w = tw.template get<S>(b, r, r * k * step);
-        if (DIR > 0) w.y = -w.y;
-        v[b * RAD + r] = cmul(v[b * RAD + r], w);
-      }
+      for (int r = 1; r < RAD; ++r) v[b * RAD + r] = cmul(v[b * RAD + r], w[r]);
     }
     dft<R, RAD, DIR>(&v[b * RAD]);
   }

@@ -32,9 +32,10 @@ def test_strang_solve(d, n):
     d_ = rel(host(out), ref)
     # rounding of the first transform weighted by the diagonal's peak-to-rms ratio; a
     # Bluestein transform rounds through three length-L FFTs (two per pencil and the
-    # kernel spectrum's) where the sine transform takes one: 4e-13 per unit of the ratio
+    # kernel spectrum's) where the sine transform takes one: three times the 2e-13 per
+    # unit of the ratio of the sine-basis factors
     g = 1.0 / P.strang_m()
-    tol = max(1e-12, 4e-13 * g.max() / np.sqrt((g ** 2).mean()))
+    tol = max(1e-12, 6e-13 * g.max() / np.sqrt((g ** 2).mean()))
     say(f"   rel diff {d_:.2e} (bound {tol:.1e})")
     assert d_ < tol
     S.close()

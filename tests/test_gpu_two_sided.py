@@ -40,9 +40,10 @@ def test_prec_forms(d, n):
         R.rsfde_apply_prec_form(S.h, 0, form, dev(r), out)
         d_ = rel(host(out), ref.ravel())
         # the rounding of the first transform (either side) reaches the result scaled
-        # by the diagonal's peak-to-rms ratio: 1e-13 per unit of that ratio, at least 1e-12
+        # by the diagonal's peak-to-rms ratio: 2e-13 per unit of that ratio (the FFT
+        # twiddles are products of two table values, two roundings), at least 1e-12
         g = diag[form]
-        tol = max(1e-12, 1e-13 * g.max() / np.sqrt((g ** 2).mean()))
+        tol = max(1e-12, 2e-13 * g.max() / np.sqrt((g ** 2).mean()))
         say(f"   form {form}: rel diff {d_:.2e} (bound {tol:.1e})")
         assert d_ < tol
     S.close()
