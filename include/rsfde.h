@@ -263,6 +263,16 @@ int rsfde_prescan_ebar(rsfde_handle h, int instance, int M);
  * Errors: RSFDE_E_INVALID_ARG, RSFDE_E_HIP. */
 int rsfde_set_graph(rsfde_handle h, int enable);
 
+/* Workgroup shape the tile autotuner picked at setup for the pencil passes of one
+ * instance along `axis`: operator passes (transform = 0) or transform passes
+ * (transform = 1), in the FP64 chains (precision = RSFDE_FP64) or the FP32 inner
+ * chains of the mixed form (RSFDE_MIXED).  *length = L = 2(N_axis + 1), the
+ * transform length; *per_workgroup = complex transforms per workgroup (two real
+ * pencils each).  The pass kernel is rsfde_pass_kernel<R, L, per_workgroup,
+ * axis > 0>.  Host only.  Errors: RSFDE_E_INVALID_ARG. */
+int rsfde_get_pass_shape(rsfde_handle h, int instance, int axis, int precision, int transform,
+                         int* length, int* per_workgroup);
+
 /* Kernel classes for HIP-event timing (bit i of the mask enables class i). */
 #define RSFDE_K_MV_FIRST    0  /* first-axis operator pass */
 #define RSFDE_K_MV_MID      1  /* middle-axis operator pass (d = 3) */

@@ -2095,6 +2095,22 @@ int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* 
   return RSFDE_OK;
 }
 
+int rsfde_get_pass_shape(rsfde_handle h, int instance, int axis, int precision, int transform,
+                         int* length, int* per_workgroup) {
+  if (!h || instance < 0 || instance >= h->count || !length || !per_workgroup) return RSFDE_E_INVALID_ARG;
+  const Inst& I = h->inst[instance];
+  if (axis < 0 || axis >= I.d || (transform != 0 && transform != 1)) return RSFDE_E_INVALID_ARG;
+  if (precision != RSFDE_FP64 && precision != RSFDE_MIXED) return RSFDE_E_INVALID_ARG;
+  const bool fp32 = precision == RSFDE_MIXED;
+  if (fp32 && I.p.precision != RSFDE_MIXED) return RSFDE_E_INVALID_ARG;
+  const int L = I.ax[axis].L;
+  int nt = 0, ppt = 0;
+  pass_shape_rt(L, fp32, axis > 0, I.var[axis][fp32 ? 1 : 0][transform], &nt, &ppt);
+  *length = L;
+  *per_workgroup = ppt / 2;
+  return RSFDE_OK;
+}
+
 int rsfde_set_graph(rsfde_handle h, int enable) {
   if (!h || (enable != 0 && enable != 1)) return RSFDE_E_INVALID_ARG;
   if (enable && !h->cap) CK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));

@@ -40,7 +40,7 @@ EXPORTED = (
     "rsfde_destroy", "rsfde_strerror", "rsfde_set_fields", "rsfde_eval_field",
     "rsfde_eval_field_batch", "rsfde_set_graph", "rsfde_apply_A",
     "rsfde_apply_prec", "rsfde_apply_prec_form", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
-    "rsfde_get_timing", "rsfde_prescan_ebar",
+    "rsfde_get_timing", "rsfde_prescan_ebar", "rsfde_get_pass_shape",
 )
 
 K_CLASSES = ("mv_first", "mv_mid", "mv_last", "dst", "dsd", "dots", "orth_dots", "orth_norm", "update")
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_set_graph.argtypes = [P, I]
     lib.rsfde_get_timing.argtypes = [P, I, C.POINTER(C.c_longlong), C.POINTER(D), C.POINTER(D)]
     lib.rsfde_prescan_ebar.argtypes = [P, I, I]
+    lib.rsfde_get_pass_shape.argtypes = [P, I, I, I, I, C.POINTER(I), C.POINTER(I)]
     for name in EXPORTED:
         getattr(lib, name)
         if name != "rsfde_strerror":
@@ -282,6 +283,14 @@ def rsfde_get_tables(h, instance: int, axis: int, N: int):
     _check(load_library().rsfde_get_tables(h, instance, axis, s.ctypes.data, q.ctypes.data, lam.ctypes.data),
            "rsfde_get_tables")
     return s, q, lam
+
+
+def rsfde_get_pass_shape(h, instance: int, axis: int, precision: int, transform: int):
+    """(L, complex transforms per workgroup) of the autotuned pencil passes."""
+    L, F = C.c_int(0), C.c_int(0)
+    _check(load_library().rsfde_get_pass_shape(h, instance, axis, precision, transform,
+                                               C.byref(L), C.byref(F)), "rsfde_get_pass_shape")
+    return L.value, F.value
 
 
 def rsfde_set_graph(h, enable: bool) -> None:

@@ -108,6 +108,7 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.rsfde_set_timing(None, 1, 1) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_set_graph(None, 1) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_apply_prec_form(None, 0, 1, None, None) == R.RSFDE_E_INVALID_ARG
+    assert lib.rsfde_get_pass_shape(None, 0, 0, 0, 0, None, None) == R.RSFDE_E_INVALID_ARG
 
 
 def test_params_from_paper_example():
