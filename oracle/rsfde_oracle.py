@@ -43,7 +43,7 @@ __all__ = [
     "fcd_weights", "fcd_weights_gamma", "toeplitz_dense", "B_dense", "sine_matrix",
     "hankel_dense", "tau_dense", "tau_eigs_cosine", "B_eigs", "riesz_poly_derivative",
     "strang_first_column", "circulant_dense", "strang_eigs",
-    "OracleProblem", "gmres_left", "run",
+    "OracleProblem", "PointOracle", "gmres_left", "run",
 ]
 
 
@@ -578,6 +578,129 @@ class OracleProblem:
                             rtol=self.inst.rtol if rtol is None else rtol,
                             max_cycles=self.inst.max_cycles if max_cycles is None else max_cycles)
         return self.apply_P_power(xt, -0.5), st
+
+
+# ----------------------------------------------------------------------------
+# Single entries of the operators on grids too large for the dense model
+# ----------------------------------------------------------------------------
+
+class PointOracle:
+    """One output entry at a time of A = B_alpha E + S_alpha (eq. tls, Salpha, Ha),
+    of B P = ebar B_alpha + tau(S_alpha) (eqs. Pa, tauSalpha, tau) and of the source
+    operator F (eq. eq2.2), by their definitions.  Only per-axis data is held
+    (FCD weights, stencil weights); a Toeplitz or Hankel row is formed when used.
+    Grid points J = (j_1, ..., j_d) are 0-based interior indices; arrays have shape
+    (N_d, ..., N_1) as in OracleProblem."""
+
+    def __init__(self, inst, ebar: float):
+        self.inst = inst
+        self.d = inst.d
+        self.N = tuple(int(v) for v in inst.n)
+        self.dt = inst.T / inst.M
+        self.h = [(inst.hi[i] - inst.lo[i]) / (self.N[i] + 1) for i in range(self.d)]
+        self.eta = [inst.kappa[i] * self.dt / (2.0 * self.h[i] ** inst.alpha[i]) for i in range(self.d)]
+        self.s = [fcd_weights(inst.alpha[i], self.N[i]) for i in range(self.d)]
+        self.ebar = float(ebar)
+
+    def _ix(self, J):
+        return tuple(reversed(J))
+
+    def _w(self, i, o):
+        a = self.inst.alpha[i]
+        return 1.0 - a / 12.0 if o == 0 else a / 24.0
+
+    def _neighbours(self, J, axes):
+        """(weight, J') of the tridiagonal stencils along `axes` (zero outside)."""
+        out = [(1.0, list(J))]
+        for i in axes:
+            nxt = []
+            for w, Jn in out:
+                for o in (-1, 0, 1):
+                    k = Jn[i] + o
+                    if 0 <= k < self.N[i]:
+                        J2 = list(Jn)
+                        J2[i] = k
+                        nxt.append((w * self._w(i, o), J2))
+            out = nxt
+        return out
+
+    def _line(self, X, J, i):
+        idx = list(self._ix(J))
+        idx[self.d - 1 - i] = slice(None)
+        return X[tuple(idx)]
+
+    def toeplitz_row(self, i, j):
+        """Row j of S_{alpha_i}: s_{|j-k|} (eq. eq0)."""
+        return self.s[i][np.abs(j - np.arange(self.N[i]))]
+
+    def hankel_row(self, i, j):
+        """Row j of H(S_{alpha_i}) (eq. tau; the reading of hankel_dense, 0-based)."""
+        N = self.N[i]
+        tt = np.zeros(2 * N + 3)
+        tt[:N] = self.s[i]
+        k = np.arange(N)
+        return tt[j + k + 2] + tt[2 * N - j - k]
+
+    def apply_A_at(self, e, X, J) -> float:
+        allx = list(range(self.d))
+        val = sum(w * e[self._ix(Jn)] * X[self._ix(Jn)] for w, Jn in self._neighbours(J, allx))
+        for i in range(self.d):
+            row = self.toeplitz_row(i, J[i])
+            for w, Jn in self._neighbours(J, [l for l in allx if l != i]):
+                val += self.eta[i] * w * float(row @ self._line(X, Jn, i))
+        return float(val)
+
+    def apply_BP_at(self, X, J) -> float:
+        allx = list(range(self.d))
+        val = self.ebar * sum(w * X[self._ix(Jn)] for w, Jn in self._neighbours(J, allx))
+        for i in range(self.d):
+            row = self.toeplitz_row(i, J[i]) - self.hankel_row(i, J[i])
+            for w, Jn in self._neighbours(J, [l for l in allx if l != i]):
+                val += self.eta[i] * w * float(row @ self._line(X, Jn, i))
+        return float(val)
+
+    def rhs_at(self, e, U, F_J: float, J) -> float:
+        """b_J = (B E u)_J - (S u)_J + dt F_J (eq. tls)."""
+        allx = list(range(self.d))
+        val = sum(w * e[self._ix(Jn)] * U[self._ix(Jn)] for w, Jn in self._neighbours(J, allx))
+        for i in range(self.d):
+            row = self.toeplitz_row(i, J[i])
+            for w, Jn in self._neighbours(J, [l for l in allx if l != i]):
+                val -= self.eta[i] * w * float(row @ self._line(U, Jn, i))
+        return float(val) + self.dt * F_J
+
+    def F_at(self, f_closure_at, J) -> float:
+        """F_J = (prod_l H_{alpha_l}) f at interior J, from f on the closure grid;
+        f_closure_at(K) gives f at closure index K (interior j <-> closure j+1)."""
+        val = 0.0
+        for w, Jn in self._closure_neighbours(J):
+            val += w * f_closure_at(Jn)
+        return float(val)
+
+    def _closure_neighbours(self, J):
+        out = [(1.0, [j + 1 for j in J])]
+        for i in range(self.d):
+            nxt = []
+            for w, Kn in out:
+                for o in (-1, 0, 1):
+                    K2 = list(Kn)
+                    K2[i] += o
+                    nxt.append((w * self._w(i, o), K2))
+            out = nxt
+        return out
+
+    def mu_bounds(self):
+        """Bounds mu_min <= mu_K <= mu_max of the eigenvalues of B P (eq. q, Lemma
+        Heig): products and sums of the per-axis extremes."""
+        lo_l, hi_l, lo_w, hi_w = 1.0, 1.0, self.ebar, self.ebar
+        for i in range(self.d):
+            lam = B_eigs(self.inst.alpha[i], self.N[i])
+            w = self.eta[i] * tau_eigs_cosine(self.s[i]) / lam
+            lo_l *= lam.min()
+            hi_l *= lam.max()
+            lo_w += w.min()
+            hi_w += w.max()
+        return lo_l * lo_w, hi_l * hi_w
 
 
 # ----------------------------------------------------------------------------

@@ -373,6 +373,35 @@ def test_T9c_theorem_one_sided_residual_bound(d, n):
         assert r1 <= r2 / math.sqrt(P.ebar) * (1 + 1e-9), (j, r1, r2)
 
 
+@pytest.mark.parametrize("d,n,alpha,kappa", [
+    (1, (11,), (1.6,), (1.0,)),
+    (2, (7, 6), (1.3, 1.7), (1.0, 0.5)),
+    (3, (5, 4, 3), (1.2, 1.5, 1.8), (1.0, 0.8, 0.6)),
+])
+def test_point_oracle_entries_equal_the_dense_model(d, n, alpha, kappa):
+    # single entries by definition (used at full sizes) against the dense model
+    P = _problem(d, n, alpha, kappa)
+    Q = O.PointOracle(P.inst, ebar=P.ebar)
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal(P.shape)
+    e = 1.0 + rng.random(P.shape)
+    A = P.apply_A(e, x)
+    BPx = (P.dense_BP() @ x.ravel()).reshape(P.shape)
+    fc = rng.standard_normal(tuple(v + 2 for v in reversed(P.N)))
+    F = P.F_from_closure(fc)
+    b = P.rhs(e, F, x)
+    for J in np.ndindex(*P.N):
+        ix = tuple(reversed(J))
+        assert Q.apply_A_at(e, x, J) == pytest.approx(A[ix], rel=1e-12, abs=1e-12)
+        assert Q.apply_BP_at(x, J) == pytest.approx(BPx[ix], rel=1e-12, abs=1e-12)
+        FJ = Q.F_at(lambda K: fc[tuple(reversed(K))], J)
+        assert FJ == pytest.approx(F[ix], rel=1e-12, abs=1e-12)
+        assert Q.rhs_at(e, x, FJ, J) == pytest.approx(b[ix], rel=1e-12, abs=1e-12)
+    mu = P.mu()
+    lo, hi = Q.mu_bounds()
+    assert lo <= mu.min() * (1 + 1e-12) and mu.max() <= hi * (1 + 1e-12)
+
+
 def test_gmres_iterate_minimises_residual_over_krylov_space():
     # Lemma Krylov: the k-th iterate minimises ||M^{-1}(b - A x)|| over x0 + K_k(M^{-1}A, z0).
     rng = np.random.default_rng(11)
