@@ -825,6 +825,7 @@ static GridDev grid_dev(const Inst& I, bool closure) {
     g.lo[i] = I.p.lo[i];
     g.h[i] = I.ax[i].h;
     g.kappa[i] = I.p.kappa[i];
+    g.inv[i] = 1.0 / (double)(closure ? I.ax[i].N + 2 : I.ax[i].N);
   }
   g.size = closure ? I.nclo : I.n;
   return g;

@@ -31,7 +31,23 @@ struct GridDev {
   int N[3];                  // interior sizes
   double lo[3], h[3];
   double kappa[3];
+  double inv[3];             // 1 / (points per axis of this grid), for index splitting
   int64_t size;
+};
+
+// (quotient, remainder) of r by n for r < 2^32, from the reciprocal inv = 1/n and
+// one correction step (no integer division).
+__device__ __forceinline__ unsigned split_u32(unsigned r, unsigned n, double inv, unsigned* rem) {
+  unsigned q = (unsigned)((double)r * inv);
+  if ((unsigned long long)q * n > r) --q;
+  else if ((unsigned long long)(q + 1) * n <= r) ++q;
+  *rem = r - q * n;
+  return q;
+}
+
+// Time factors of the field families, evaluated once per workgroup.
+struct TimeF {
+  double cos_t, exp_mt;
 };
 
 // one instance's field evaluation and its source operator, for batched launches

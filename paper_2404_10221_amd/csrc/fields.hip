@@ -32,14 +32,14 @@ __device__ __forceinline__ double sine_modes(const FieldDev& F, int d, const int
 }
 
 __device__ __forceinline__ double e_value(const FieldDev& E, int d, const double* x, const int* jc,
-                                          const int* Ncl, double t) {
+                                          const int* Ncl, double t, const TimeF& tf) {
   switch (E.kind) {
     case RSFDE_FIELD_CONST:
       return E.c[0];
     case RSFDE_FIELD_SUMSQ_EXP: {
       double s = 0.0;
       for (int i = 0; i < d; ++i) s += x[i] * x[i];
-      return (s + exp(-t)) / E.c[0];
+      return (s + tf.exp_mt) / E.c[0];
     }
     case RSFDE_FIELD_POLY_T: {
       double p = 1.0;  // prod_i x_i^c3 (table row AX_E)
@@ -49,7 +49,7 @@ __device__ __forceinline__ double e_value(const FieldDev& E, int d, const double
     case RSFDE_FIELD_SINPROD_COS: {
       double p = 1.0;  // prod_i sin(pi x_i) (table row AX_E)
       for (int i = 0; i < d; ++i) p *= E.ax[i][AX_E * Ncl[i] + jc[i]];
-      return E.c[0] + E.c[1] * p * cos(t);
+      return E.c[0] + E.c[1] * p * tf.cos_t;
     }
     case RSFDE_FIELD_SINE_FIELD: {
       const double g = sine_modes(E, d, jc, Ncl);
@@ -58,6 +58,14 @@ __device__ __forceinline__ double e_value(const FieldDev& E, int d, const double
     default:
       return 0.0;
   }
+}
+
+// cos t and exp(-t) by one thread of the workgroup (every thread reaches the barrier)
+__device__ __forceinline__ TimeF time_factors(double t) {
+  __shared__ TimeF tfs;
+  if (threadIdx.x == 0) tfs = TimeF{cos(t), exp(-t)};
+  __syncthreads();
+  return tfs;
 }
 
 __device__ __forceinline__ double poly_p(double x, int a) {
@@ -80,8 +88,8 @@ __device__ __forceinline__ double riesz_poly(const double* mc, double alpha, int
 }
 
 __device__ __forceinline__ void fields_eval_at(const FieldDev& E, const FieldDev& F, int which,
-                                               const GridDev& g, double t, double* __restrict__ out,
-                                               int64_t idx) {
+                                               const GridDev& g, double t, const TimeF& tf,
+                                               double* __restrict__ out, int64_t idx) {
   if (idx >= g.size) return;
   const int d = g.d;
   int jc[3] = {0, 0, 0};
@@ -92,9 +100,7 @@ __device__ __forceinline__ void fields_eval_at(const FieldDev& E, const FieldDev
     const unsigned ni = (unsigned)(g.closure ? g.N[i] + 2 : g.N[i]);
     unsigned ji;
     if (r < 0xffffffffull) {
-      const unsigned r32 = (unsigned)r;
-      ji = r32 % ni;
-      r = r32 / ni;
+      r = split_u32((unsigned)r, ni, g.inv[i], &ji);
     } else {
       ji = (unsigned)(r % ni);
       r /= ni;
@@ -105,19 +111,19 @@ __device__ __forceinline__ void fields_eval_at(const FieldDev& E, const FieldDev
   }
   double v = 0.0;
   if (which == RSFDE_WHICH_E) {
-    v = e_value(E, d, x, jc, Ncl, t);
+    v = e_value(E, d, x, jc, Ncl, t, tf);
   } else if (which == RSFDE_WHICH_F) {
     if (F.kind == RSFDE_FIELD_SINE_MODES) {
       v = sine_modes(F, d, jc, Ncl);
     } else if (F.kind == RSFDE_FIELD_MANUFACTURED) {
-      const double A = F.c[0] * exp(-t);
+      const double A = F.c[0] * tf.exp_mt;
       double pr[3];
       double u = A;
       for (int i = 0; i < d; ++i) {
         pr[i] = F.ax[i][AX_U * Ncl[i] + jc[i]];  // x_i^a (1 - x_i)^a
         u *= pr[i];
       }
-      const double ev = e_value(E, d, x, jc, Ncl, t);
+      const double ev = e_value(E, d, x, jc, Ncl, t, tf);
       v = -ev * u;  // e u_t, u_t = -u
       for (int i = 0; i < d; ++i) {
         double other = A;
@@ -139,7 +145,8 @@ __device__ __forceinline__ void fields_eval_at(const FieldDev& E, const FieldDev
 __global__ void __launch_bounds__(256)
 k_fields_eval(const FieldDev E, const FieldDev F, int which, const GridDev g, double t,
               double* __restrict__ out) {
-  fields_eval_at(E, F, which, g, t, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const TimeF tf = time_factors(t);
+  fields_eval_at(E, F, which, g, t, tf, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // one launch for many instances: job[s] covers blocks start[s] .. start[s+1)
@@ -147,7 +154,8 @@ __global__ void __launch_bounds__(256)
 k_fields_eval_b(const FieldJob* __restrict__ jobs, const int* __restrict__ start, int n, double t) {
   const int slot = batch_slot(start, n, blockIdx.x);
   const FieldJob& J = jobs[slot];
-  fields_eval_at(J.e, J.f, J.which, J.g, t, J.out,
+  const TimeF tf = time_factors(t);
+  fields_eval_at(J.e, J.f, J.which, J.g, t, tf, J.out,
                  (int64_t)((int)blockIdx.x - start[slot]) * blockDim.x + threadIdx.x);
 }
 
@@ -209,22 +217,22 @@ hipError_t fields_sintab(int K, int Ncl, double lo, double h, double* tab, hipSt
 // F_J = sum over the 3^d neighbours of prod_i w_i(a_i) f_{J+a} on the closure
 // grid, w(0) = 1 - alpha_i/12, w(+-1) = alpha_i/24 (every interior index lies
 // inside the stencil's support, so H acts as the stencil on each axis).
-__device__ __forceinline__ void compute_F_at(const double* __restrict__ fcl, const GridDev& g,
-                                             double a0, double a1, double a2,
-                                             double* __restrict__ F, int64_t idx) {
+template <int D>
+__device__ __forceinline__ void compute_F_d(const double* __restrict__ fcl, const GridDev& g,
+                                            const double (&al)[3], double* __restrict__ F,
+                                            int64_t idx) {
   if (idx >= g.size) return;
-  const int d = g.d;
-  const double al[3] = {a0, a1, a2};
   int j[3] = {0, 0, 0};
   int64_t sc[3] = {0, 0, 0};
   uint64_t r = (uint64_t)idx;
   int64_t stride = 1;
-  for (int i = 0; i < d; ++i) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
     const unsigned ni = (unsigned)g.N[i];
     if (r < 0xffffffffull) {
-      const unsigned r32 = (unsigned)r;
-      j[i] = (int)(r32 % ni) + 1;
-      r = r32 / ni;
+      unsigned ji;
+      r = split_u32((unsigned)r, ni, g.inv[i], &ji);
+      j[i] = (int)ji + 1;
     } else {
       j[i] = (int)(r % ni) + 1;
       r /= ni;
@@ -233,24 +241,46 @@ __device__ __forceinline__ void compute_F_at(const double* __restrict__ fcl, con
     stride *= (g.N[i] + 2);
   }
   int64_t c0 = 0;
-  for (int i = 0; i < d; ++i) c0 += (int64_t)j[i] * sc[i];
+#pragma unroll
+  for (int i = 0; i < D; ++i) c0 += (int64_t)j[i] * sc[i];
   double w[3][3];
+#pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const double a = i < d ? al[i] : 0.0;
+    const double a = i < D ? al[i] : 0.0;
     w[i][0] = a / 24.0;
-    w[i][1] = i < d ? 1.0 - a / 12.0 : 1.0;
+    w[i][1] = i < D ? 1.0 - a / 12.0 : 1.0;
     w[i][2] = a / 24.0;
   }
-  double acc = 0.0;
-  const int n2 = d >= 2 ? 3 : 1, n3 = d >= 3 ? 3 : 1;
-  for (int c = 0; c < n3; ++c) {
+  // all 3^D loads in flight together; the sums in the same order as written
+  constexpr int n2 = D >= 2 ? 3 : 1, n3 = D >= 3 ? 3 : 1;
+  double fv[n3][n2][3];
+#pragma unroll
+  for (int c = 0; c < n3; ++c)
+#pragma unroll
     for (int b = 0; b < n2; ++b) {
-      const double wbc = (d >= 3 ? w[2][c] : 1.0) * (d >= 2 ? w[1][b] : 1.0);
-      const int64_t off = c0 + (d >= 3 ? (int64_t)(c - 1) * sc[2] : 0) + (d >= 2 ? (int64_t)(b - 1) * sc[1] : 0);
-      acc += wbc * (w[0][0] * fcl[off - 1] + w[0][1] * fcl[off] + w[0][2] * fcl[off + 1]);
+      const int64_t off = c0 + (D >= 3 ? (int64_t)(c - 1) * sc[2] : 0) + (D >= 2 ? (int64_t)(b - 1) * sc[1] : 0);
+      fv[c][b][0] = fcl[off - 1];
+      fv[c][b][1] = fcl[off];
+      fv[c][b][2] = fcl[off + 1];
     }
-  }
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < n3; ++c)
+#pragma unroll
+    for (int b = 0; b < n2; ++b) {
+      const double wbc = (D >= 3 ? w[2][c] : 1.0) * (D >= 2 ? w[1][b] : 1.0);
+      acc += wbc * (w[0][0] * fv[c][b][0] + w[0][1] * fv[c][b][1] + w[0][2] * fv[c][b][2]);
+    }
   F[idx] = acc;
+}
+
+__device__ __forceinline__ void compute_F_at(const double* __restrict__ fcl, const GridDev& g,
+                                             double a0, double a1, double a2,
+                                             double* __restrict__ F, int64_t idx) {
+  const double al[3] = {a0, a1, a2};
+  if (g.d == 1) compute_F_d<1>(fcl, g, al, F, idx);
+  else if (g.d == 2) compute_F_d<2>(fcl, g, al, F, idx);
+  else compute_F_d<3>(fcl, g, al, F, idx);
 }
 
 __global__ void __launch_bounds__(256)
