@@ -262,8 +262,29 @@ __device__ __forceinline__ void tw_powers(const TW& tw, int m, cpx<R>* w) {
   }
 }
 
+// Barrier inside one transform.  When the T threads of a transform lie in one
+// wavefront (T divides 64), that wavefront's LDS accesses are performed in
+// program order, so a wavefront-scope fence and a wave barrier (which only stops
+// the compiler from moving memory accesses across it) take the place of the
+// workgroup barrier: the wavefronts of a workgroup then run their transforms
+// without waiting for each other.  `last` marks the barrier after the final
+// stage, which stays a workgroup barrier: callers read other wavefronts'
+// results there.
+template <int L>
+__device__ __forceinline__ void stage_sync(bool last) {
+  if constexpr (64 % FftPlan<L>::T == 0) {
+    if (!last) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      return;
+    }
+  }
+  __syncthreads();
+}
+
 // One Stockham stage on the thread's part of one transform held in LDS;
-// twl is the LDS twiddle table filled by twiddle_fill.
+// tw reads the LDS twiddle table that tw_store filled.
 template <typename R, int L, int DIR, int S, typename TW>
 __device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const TW& tw) {
   using P = FftPlan<L>;
@@ -303,7 +324,7 @@ __device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const T
     }
     dft<R, RAD, DIR>(&v[b * RAD]);
   }
-  __syncthreads();
+  stage_sync<L>(false);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = t + b * T;
@@ -316,7 +337,7 @@ __device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const T
       else buf[base + r * Ns] = v[b * RAD + r];
     }
   }
-  __syncthreads();
+  stage_sync<L>(S + 1 == FftPlan<L>::NS);
 }
 
 template <typename R, int L, int DIR, int S, typename TW>
