@@ -31,8 +31,8 @@ KCLASS_KERNELS = {
     "mv_first": "rsfde_pass_kernel, first-axis operator pass (B stencil on e.v and v, Toeplitz product)",
     "mv_mid": "rsfde_pass_kernel, middle-axis operator pass",
     "mv_last": "rsfde_pass_kernel, last-axis operator pass (B stencil, Toeplitz product, sine transform)",
-    "dst": "rsfde_pass_kernel, sine-transform pass",
-    "dsd": "rsfde_pass_kernel, sine transform + 1/mu scaling + sine transform",
+    "dst": "rsfde_dst_kernel, sine-transform pass",
+    "dsd": "rsfde_dst_kernel, sine transform + 1/mu scaling + sine transform",
     "dots": "k_sweep1 (CGS2 sweep 1)",
     "orth_dots": "k_sweep2 (CGS2 sweep 2)",
     "orth_norm": "k_sweep3 (CGS2 sweep 3)",
@@ -62,7 +62,8 @@ def pass_symbol(R, h, inst, kclass: str):
     if where is None or where[0] >= d:
         return None
     L, F = R.rsfde_get_pass_shape(h, 0, where[0], R.RSFDE_FP64, where[1])
-    return f"rsfde_pass_kernel<double, {L}, {F}, {'true' if where[0] > 0 else 'false'}>"
+    kern = "rsfde_dst_kernel" if where[1] else "rsfde_pass_kernel"
+    return f"{kern}<double, {L}, {F}, {'true' if where[0] > 0 else 'false'}>"
 
 
 def kernel_source_hash() -> str:

@@ -225,6 +225,7 @@ struct BGroup {
   const BPass* desc = nullptr;  // device copies (batch descriptor buffer)
   const int* start = nullptr;
   int cls = 0;
+  bool mv = false;  // operator pass (else sine transform); one op per group
   double bytes = 0;
 };
 struct BChain {
@@ -1129,6 +1130,7 @@ static int plan_chain(rsfde_ctx* h, int r, const std::vector<int>& S, RecFn rec_
       g.fp32 = r0.fp32;
       g.strided = r0.a.axis > 0;
       g.cls = op_class(r0.a.op);
+      g.mv = r0.a.op <= OP_MV_LAST;
       std::vector<BPass> desc;
       std::vector<int> start(1, 0);
       for (size_t s = s0; s < S.size(); ++s) {
@@ -1175,6 +1177,7 @@ static int launch_chain_batched(rsfde_ctx* h, const BChain& c, int j, int pend) 
       bl.ninst = g.ninst;
       bl.j = j;
       bl.pend = pend;
+      bl.mv = g.mv ? 1 : 0;
       CKS(timed_launch(h, g.cls, g.bytes, [&](hipEvent_t ea, hipEvent_t eb) {
         return launch_pass_batched(g.L, g.fp32, bl, g.nblocks, g.strided, g.var, h->stream, ea, eb);
       }));

@@ -283,37 +283,45 @@ __device__ __forceinline__ void stage_sync(bool last) {
   __syncthreads();
 }
 
-// One Stockham stage on the thread's part of one transform held in LDS;
-// tw reads the LDS twiddle table that tw_store filled.
-template <typename R, int L, int DIR, int S, typename TW>
-__device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const TW& tw) {
+// One Stockham stage on the thread's part of one transform held in LDS, split
+// into its LDS reads, its arithmetic and its LDS writes.  The thread holds E
+// values in v: slot b R + r is element t + T (b + NB r) of the stage's input
+// (before the arithmetic) and of its output (after it, for the last stage).
+template <typename R, int L, int S>
+struct StageGeom {
   using P = FftPlan<L>;
-  constexpr int RAD = P::R[S];
-  constexpr int Ns = StageNs<L, S>::value;
-  constexpr int T = P::T, E = P::E, NB = E / RAD, LR = L / RAD;
+  static constexpr int RAD = P::R[S], Ns = StageNs<L, S>::value;
+  static constexpr int T = P::T, E = P::E, NB = E / RAD, LR = L / RAD;
   static_assert(E % RAD == 0, "radix must divide the per-thread element count");
-  cpx<R> v[E];
+  // slot of element t + T m in the stage's register layout
+  static constexpr int slot(int m) { return (m % NB) * RAD + m / NB; }
+};
+
+template <typename R, int L, int S>
+__device__ __forceinline__ void stage_read(const LdsSeq<R, L> buf, int t, cpx<R>* v) {
+  using G = StageGeom<R, L, S>;
   using Q = LdsSeq<R, L>;
-  constexpr int BS = Q::BS;
+  constexpr int BS = Q::BS, LR = G::LR;
   // Reads x[j + r L/R]: when L/R is a whole number of rows, pos(j + r L/R) =
   // pos(j) + r (L/R + L/(R BS)), a constant offset per r.
   constexpr bool rd_fold = LR % BS == 0;
-  // Writes y[base + r Ns], base = (j/Ns) Ns R + j mod Ns: the row of base + r Ns
-  // is the row of base plus (r Ns)/BS when Ns is a multiple of BS, or Ns divides
-  // BS and Ns R is a multiple or a divisor of BS (no carry out of the row).
-  constexpr bool wr_fold =
-      Ns % BS == 0 || (BS % Ns == 0 && ((Ns * RAD) % BS == 0 || BS % (Ns * RAD) == 0));
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int j = t + b * T;
+  for (int b = 0; b < G::NB; ++b) {
+    const int j = t + b * G::T;
     const int pj = Q::pos(j);
 #pragma unroll
-    for (int r = 0; r < RAD; ++r)
-      v[b * RAD + r] = rd_fold ? buf.p[pj + r * (LR + LR / BS)] : buf[j + r * LR];
+    for (int r = 0; r < G::RAD; ++r)
+      v[b * G::RAD + r] = rd_fold ? buf.p[pj + r * (LR + LR / BS)] : buf[j + r * LR];
   }
+}
+
+template <typename R, int L, int DIR, int S, typename TW>
+__device__ __forceinline__ void stage_math(int t, const TW& tw, cpx<R>* v) {
+  using G = StageGeom<R, L, S>;
+  constexpr int RAD = G::RAD, Ns = G::Ns;
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int j = t + b * T;
+  for (int b = 0; b < G::NB; ++b) {
+    const int j = t + b * G::T;
     if constexpr (Ns > 1) {
       const int k = j % Ns;
       constexpr int step = L / (Ns * RAD);
@@ -324,10 +332,21 @@ __device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const T
     }
     dft<R, RAD, DIR>(&v[b * RAD]);
   }
-  stage_sync<L>(false);
+}
+
+template <typename R, int L, int S>
+__device__ __forceinline__ void stage_write(const LdsSeq<R, L> buf, int t, const cpx<R>* v) {
+  using G = StageGeom<R, L, S>;
+  using Q = LdsSeq<R, L>;
+  constexpr int BS = Q::BS, RAD = G::RAD, Ns = G::Ns;
+  // Writes y[base + r Ns], base = (j/Ns) Ns R + j mod Ns: the row of base + r Ns
+  // is the row of base plus (r Ns)/BS when Ns is a multiple of BS, or Ns divides
+  // BS and Ns R is a multiple or a divisor of BS (no carry out of the row).
+  constexpr bool wr_fold =
+      Ns % BS == 0 || (BS % Ns == 0 && ((Ns * RAD) % BS == 0 || BS % (Ns * RAD) == 0));
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int j = t + b * T;
+  for (int b = 0; b < G::NB; ++b) {
+    const int j = t + b * G::T;
     const int k = j % Ns;
     const int base = (j / Ns) * Ns * RAD + k;
     const int pb = Q::pos(base);
@@ -337,6 +356,15 @@ __device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const T
       else buf[base + r * Ns] = v[b * RAD + r];
     }
   }
+}
+
+template <typename R, int L, int DIR, int S, typename TW>
+__device__ __forceinline__ void fft_stage(const LdsSeq<R, L> buf, int t, const TW& tw) {
+  cpx<R> v[FftPlan<L>::E];
+  stage_read<R, L, S>(buf, t, v);
+  stage_math<R, L, DIR, S>(t, tw, v);
+  stage_sync<L>(false);
+  stage_write<R, L, S>(buf, t, v);
   stage_sync<L>(S + 1 == FftPlan<L>::NS);
 }
 
@@ -354,4 +382,46 @@ __device__ __forceinline__ void fft_stages(const LdsSeq<R, L> buf, int t, const 
 template <typename R, int L, int DIR, typename TW>
 __device__ __forceinline__ void fft_lds(const LdsSeq<R, L> buf, int t, const TW& tw) {
   fft_stages<R, L, DIR, 0>(buf, t, tw);
+}
+
+// Stages 1 .. NS-2 of a transform whose first stage wrote to LDS.
+template <typename R, int L, int DIR, int S, typename TW>
+__device__ __forceinline__ void fft_mid_stages(const LdsSeq<R, L> buf, int t, const TW& tw) {
+  if constexpr (S + 1 < FftPlan<L>::NS) {
+    cpx<R> v[FftPlan<L>::E];
+    stage_read<R, L, S>(buf, t, v);
+    stage_math<R, L, DIR, S>(t, tw, v);
+    stage_sync<L>(false);
+    stage_write<R, L, S>(buf, t, v);
+    stage_sync<L>(false);
+    fft_mid_stages<R, L, DIR, S + 1>(buf, t, tw);
+  }
+}
+
+// Transform with its input and output in registers: on entry c[m] is element
+// t + T m of the sequence (m < E), on exit c[m] is element t + T m of its
+// transform.  Those are the first stage's inputs and the last stage's outputs
+// of thread t, so only the stages in between go through LDS.  FRESH: the LDS
+// sequence has not been read since the last workgroup barrier, and the twiddle
+// table still needs one (taken after the first stage's writes); otherwise a
+// previous register transform of the same threads has just read it.
+template <typename R, int L, int DIR, bool FRESH, typename TW>
+__device__ __forceinline__ void fft_regs(const LdsSeq<R, L> buf, int t, const TW& tw, cpx<R>* c) {
+  using P = FftPlan<L>;
+  constexpr int E = P::E, NS = P::NS;
+  cpx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[StageGeom<R, L, 0>::slot(m)] = c[m];
+  stage_math<R, L, DIR, 0>(t, tw, v);
+  if constexpr (NS > 1) {
+    if constexpr (!FRESH) stage_sync<L>(false);
+    stage_write<R, L, 0>(buf, t, v);
+    if constexpr (FRESH) __syncthreads();
+    else stage_sync<L>(false);
+    fft_mid_stages<R, L, DIR, 1>(buf, t, tw);
+    stage_read<R, L, NS - 1>(buf, t, v);
+    stage_math<R, L, DIR, NS - 1>(t, tw, v);
+  }
+#pragma unroll
+  for (int m = 0; m < E; ++m) c[m] = v[StageGeom<R, L, NS - 1>::slot(m)];
 }

@@ -133,17 +133,24 @@ struct PassShape {
   static constexpr int NT = F * T;
 };
 
+// Which ops a kernel carries: the operator passes or the sine-transform passes
+// (two kernels, each with the registers of its own path).
+enum : int { PK_MV = 1, PK_TR = 2 };
+
 // The pass on one tile; `bid` is the workgroup's index within the pass (the
 // block index of a single-instance launch, the local index in a batched one).
-template <typename R, int L, int F, bool STRIDED>
+template <typename R, int L, int F, bool STRIDED, int MODE>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) {
+  constexpr bool mv_op = MODE == PK_MV;  // (the launcher picks the kernel by op)
   using P = FftPlan<L>;
   constexpr int T = P::T, E = P::E, NT = F * T, PT = 2 * F;
   constexpr int LP = LdsPitch<R, L, F>::value;
   constexpr int NE = STRIDED ? E : E / 2;  // element slots per thread
   __shared__ cpx<R> lds[F * LP];
   __shared__ cpx<R> twl[TwHalf<R, L>::size];
-  __shared__ R chs[L];  // circulant spectrum / L (operator passes)
+  // circulant spectrum / L (operator passes), or the axis-0 tables of OP_DSD;
+  // not used by the strided sine-transform kernel
+  __shared__ R chs[STRIDED && MODE == PK_TR ? 1 : L];
 
   const int tid = threadIdx.x;
   const TwHalf<R, L> tw{twl};
@@ -195,22 +202,31 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   // with no branch around them: one memory latency then covers the whole load
   // phase, and it overlaps the prologue below (slots past the pencil end or the
   // tile's last pencil are loaded from a valid address and discarded).
+  // Contiguous sine-transform passes load elements t + T m of the odd extension
+  // instead (see the register-staged transforms below): lc gets x_{p-1} and la
+  // the mirrored x_{N-p}, p = t + T i < L/2.
   constexpr int NL = STRIDED ? NE : 2 * NE;  // values per input array per thread
   R lc[NL], la[NL];
   {
-    const bool ld_a = a.op <= OP_MV_LAST;
+    const bool ld_a = mv_op;
     if constexpr (!STRIDED) {
       const int64_t r0 = 2 * f < nvalid ? c_row(0) : 0;
       const int64_t r1 = 2 * f + 1 < nvalid ? c_row(1) : 0;
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         const int p = t + i * T;
-        const int pc = p < N ? p : 0;
-        lc[2 * i] = ld_any<R>(a.in_c, r0 * N + pc, in64);
-        lc[2 * i + 1] = ld_any<R>(a.in_c, r1 * N + pc, in64);
         if (ld_a) {
+          const int pc = p < N ? p : 0;
+          lc[2 * i] = ld_any<R>(a.in_c, r0 * N + pc, in64);
+          lc[2 * i + 1] = ld_any<R>(a.in_c, r1 * N + pc, in64);
           la[2 * i] = ld_any<R>(a.in_a, r0 * N + pc, false);
           la[2 * i + 1] = ld_any<R>(a.in_a, r1 * N + pc, false);
+        } else {
+          const int pc = p >= 1 ? p - 1 : 0;  // p <= N here
+          lc[2 * i] = ld_any<R>(a.in_c, r0 * N + pc, in64);
+          lc[2 * i + 1] = ld_any<R>(a.in_c, r1 * N + pc, in64);
+          la[2 * i] = ld_any<R>(a.in_c, r0 * N + (N - 1 - pc), in64);
+          la[2 * i + 1] = ld_any<R>(a.in_c, r1 * N + (N - 1 - pc), in64);
         }
       }
     } else {
@@ -229,13 +245,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   // eta q / lambda (next N) of the transform-scale-transform pass, plus that
   // pass's per-pencil factors from the other (already transformed) axes.
   constexpr int CH = (L + NT - 1) / NT;
-  const bool is_dsd = a.op == OP_DSD;
+  // (the 1/mu scaling runs along the contiguous axis only)
+  const bool is_dsd = !STRIDED && !mv_op && a.op == OP_DSD;
   R lt[CH];
   R twr[TwFill<R, L, NT>::C], twi[TwFill<R, L, NT>::C];
   tw_load<R, L, NT>(twr, twi, (const cpx<R>*)a.tw, tid);
   R rl[2][2], rw[2][2];  // [pencil of the pair][axis 1, 2]: lambda and eta q / lambda
   R ebv = (R)0;
-  if (a.op <= OP_MV_LAST) {
+  if (mv_op) {
     const R* __restrict__ cg = (const R*)a.chat;
     static_for<CH>([&](auto q) {
       const int k = tid + q.value * NT;
@@ -286,7 +303,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   const R bd = (R)a.bd, bo = (R)a.bo, eta = (R)a.eta;
   const R* __restrict__ chat = chs;
   tw_store<R, L, NT>(twr, twi, twl, tid);
-  if (a.op <= OP_MV_LAST || is_dsd) {
+  if (mv_op || is_dsd) {
     static_for<CH>([&](auto q) {
       const int k = tid + q.value * NT;
       if (L % NT == 0 || k < L) chs[k] = lt[q.value];
@@ -299,9 +316,72 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   (void)rs;
 
   const int op = a.op;
-  const bool is_mv = op <= OP_MV_LAST;
+  const bool is_mv = mv_op;
   bool dst_phase = !is_mv;          // a sine transform follows
-  bool scale_phase = op == OP_DSD;  // and a 1/mu scaling + second transform
+  bool scale_phase = is_dsd;        // and a 1/mu scaling + second transform
+
+  if constexpr (!STRIDED && !mv_op) {
+    // ---- register-staged sine transforms along a contiguous axis.  Thread t
+    // holds elements k = t + T m (m < E) of its packed pair; the odd extension
+    // z_k = x_{k-1} (1 <= k <= N), z_{L-k} = -z_k, z_0 = z_{N+1} = 0 comes
+    // straight from the loads, and fft_regs leaves Z_k at the same k.
+    cpx<R> c[E];
+    {
+      const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const bool live = t + i * T >= 1;
+        const R x0 = live && v0 ? lc[2 * i] : (R)0, x1 = live && v1 ? lc[2 * i + 1] : (R)0;
+        const R y0 = live && v0 ? la[2 * i] : (R)0, y1 = live && v1 ? la[2 * i + 1] : (R)0;
+        c[i] = cpx<R>{x0, x1};             // k = p = t + T i
+        c[NE + i] = cpx<R>{-y0, -y1};      // k = L/2 + p: -z_{N+1-p}
+      }
+    }
+    fft_regs<R, L, -1, true>(buf, t, tw, c);
+    if (scale_phase) {
+      // 1/mu_K (or a two-sided factor) on the sine coefficients, as in the LDS
+      // form below.  The coefficients of the odd extension satisfy
+      // Z_{L-k} = -Z_k, so applying the factor of index L-k to Z_k at k > L/2
+      // gives the odd extension of the scaled sequence in place.
+      const R ps = (R)a.pscale;
+      const int pm = a.pmode;
+      R Lam[2], Sig[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        Lam[q] = ((R)1 * rl[q][0]) * rl[q][1];
+        Sig[q] = ((R)0 + rw[q][0]) + rw[q][1];
+      }
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int p = t + (m % NE) * T;             // distance from 0 or from L/2
+        const bool live = p >= 1;
+        const int idx = live ? (m < NE ? p - 1 : N - p) : 0;  // sine index, < N
+        const R l0 = chs[idx], w0 = chs[N + idx];
+        R g0 = ebv + w0 + Sig[0], g1 = ebv + w0 + Sig[1];  // mu / Lambda
+        if (pm != PM_BP_INV) {
+          g0 = sqrt(g0);
+          g1 = sqrt(g1);
+        }
+        const R s0 = ps / (pm == PM_PH ? g0 : Lam[0] * l0 * g0);
+        const R s1 = ps / (pm == PM_PH ? g1 : Lam[1] * l0 * g1);
+        const cpx<R> Z = c[m];
+        c[m] = live ? cpx<R>{-Z.y * s0, Z.x * s1} : cpx<R>{0, 0};
+      }
+      fft_regs<R, L, -1, false>(buf, t, tw, c);
+    }
+    // 2 DST(x0) = -Im Z_k, 2 DST(x1) = Re Z_k at k = t + T i (1 <= k <= N)
+    const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+    const int64_t b0 = c_row(0) * N - 1, b1 = c_row(1) * N - 1;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int k = t + i * T;
+      if (k >= 1) {
+        if (v0) st_any<R>(a.out_a, b0 + k, -c[i].y, out64);
+        if (v1) st_any<R>(a.out_a, b1 + k, c[i].x, out64);
+      }
+    }
+    return;
+  }
 
   if (is_mv) {
     const bool ev_mode = op == OP_MV_FIRST || (a.flags & FL_FIRST_IS_LAST);
@@ -494,25 +574,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
     }
     __syncthreads();
   } else {
-    // ---- OP_DST / OP_DSD: load the odd extension of the input
+    // ---- OP_DST / OP_DSD along a strided axis (the contiguous form returned
+    // above): load the odd extension of the input
     if (t == 0) {
       buf[0] = cpx<R>{0, 0};
       buf[N + 1] = cpx<R>{0, 0};
     }
-    if constexpr (!STRIDED) {
-      const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
-#pragma unroll
-      for (int i = 0; i < NE; ++i) {
-        const int p = t + i * T;
-        if (p < N) {
-          R x0 = v0 ? lc[2 * i] : (R)0;
-          R x1 = v1 ? lc[2 * i + 1] : (R)0;
-          cpx<R> z{x0, x1};
-          buf[p + 1] = z;
-          buf[L - 1 - p] = -z;
-        }
-      }
-    } else {
+    if constexpr (STRIDED) {
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         int p, pp;
@@ -540,38 +608,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
     const R ps = (R)a.pscale;
     const int pm = a.pmode;
     if constexpr (!STRIDED) {
-      R eb, Lam[2], Sig[2], l0v[NE], w0v[NE];
-      if (is_dsd) {
-        // lambda and eta q / lambda of axis 0 are in chs[0, N) and chs[N, 2N)
-        eb = ebv;
+      // one-axis operator pass followed by the preconditioner (the contiguous
+      // OP_DSD returned above): chs holds the circulant spectrum, the tables come
+      // from global memory
+      const R eb = (R)(*a.ebar);
+      const R Lam[2] = {(R)1, (R)1}, Sig[2] = {(R)0, (R)0};
+      R l0v[NE], w0v[NE];
+      const R* __restrict__ lam0 = (const R*)a.lam[0];
+      const R* __restrict__ wq0 = (const R*)a.wq[0];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          Lam[c] = ((R)1 * rl[c][0]) * rl[c][1];
-          Sig[c] = ((R)0 + rw[c][0]) + rw[c][1];
-        }
-#pragma unroll
-        for (int i = 0; i < NE; ++i) {
-          const int pc = t + i * T < N ? t + i * T : 0;
-          l0v[i] = chs[pc];
-          w0v[i] = chs[N + pc];
-        }
-      } else {
-        // one-axis operator pass followed by the preconditioner: chs holds the
-        // circulant spectrum, the tables come from global memory (one batch)
-        eb = (R)(*a.ebar);
-        const R* __restrict__ lam0 = (const R*)a.lam[0];
-        const R* __restrict__ wq0 = (const R*)a.wq[0];
-#pragma unroll
-        for (int i = 0; i < NE; ++i) {
-          const int pc = t + i * T < N ? t + i * T : 0;
-          l0v[i] = lam0[pc];
-          w0v[i] = wq0[pc];
-        }
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          Lam[c] = (R)1;
-          Sig[c] = (R)0;
-        }
+      for (int i = 0; i < NE; ++i) {
+        const int pc = t + i * T < N ? t + i * T : 0;
+        l0v[i] = lam0[pc];
+        w0v[i] = wq0[pc];
       }
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
@@ -637,10 +686,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
 
 // Register budget of 128 VGPRs (4 waves per SIMD): measured faster on HBM-bound
 // grids than the unconstrained allocation (3 waves per SIMD) despite a few spills.
+// The operator passes (OP_MV_*) ...
 template <typename R, int L, int F, bool STRIDED>
 __global__ void __launch_bounds__(F * FftPlan<L>::T) __attribute__((amdgpu_waves_per_eu(4)))
 rsfde_pass_kernel(const PassArgs a) {
-  pass_body<R, L, F, STRIDED>(a, blockIdx.x);
+  pass_body<R, L, F, STRIDED, PK_MV>(a, blockIdx.x);
+}
+
+// ... and the sine-transform passes (OP_DST, OP_DSD).
+template <typename R, int L, int F, bool STRIDED>
+__global__ void __launch_bounds__(F * FftPlan<L>::T) __attribute__((amdgpu_waves_per_eu(4)))
+rsfde_dst_kernel(const PassArgs a) {
+  pass_body<R, L, F, STRIDED, PK_TR>(a, blockIdx.x);
 }
 
 // ---- batched passes: one launch covers the same pass of many instances that
@@ -660,9 +717,10 @@ struct BLaunch {
   const int* start;    // start[s] = first block of slot s; start[ninst] = grid size
   int ninst;
   int j, pend;         // Arnoldi step and pending resolve of this launch
+  int mv;              // every slot runs the same op: an operator pass (1) or a sine transform (0)
 };
 
-template <typename R, int L, int F, bool STRIDED>
+template <typename R, int L, int F, bool STRIDED, int MODE>
 __global__ void __launch_bounds__(F * FftPlan<L>::T) __attribute__((amdgpu_waves_per_eu(4)))
 rsfde_pass_batched(const BLaunch bl) {
   const int slot = batch_slot(bl.start, bl.ninst, blockIdx.x);
@@ -676,7 +734,7 @@ rsfde_pass_batched(const BLaunch bl) {
     a.gm.pend = bl.pend;
   }
   if (d.patch & BP_STOP) a.stop_fl = a.stop_fl + bl.j;
-  pass_body<R, L, F, STRIDED>(a, (int64_t)blockIdx.x - bl.start[slot]);
+  pass_body<R, L, F, STRIDED, MODE>(a, (int64_t)blockIdx.x - bl.start[slot]);
 }
 
 // Host launcher for one (precision, length); defined in the per-length
@@ -712,34 +770,44 @@ inline void pass_shape(bool strided, int var, int* nt, int* pencils_per_tile) {
   *pencils_per_tile = 0;
 }
 
+// One launch of kernel K<R, L, F, STRIDED> in the tile shape of variant V.
+#define RSFDE_LAUNCH_ONE(K, R, L, V, STR)                                                       \
+  {                                                                                             \
+    using S = PassShape<R, L, STR, V>;                                                          \
+    if (ea) hipExtLaunchKernelGGL((K<R, L, S::F, STR>), dim3((unsigned)a.nlaunch), dim3(S::NT), \
+                                  0, s, ea, eb, 0, a);                                          \
+    else hipLaunchKernelGGL((K<R, L, S::F, STR>), dim3((unsigned)a.nlaunch), dim3(S::NT), 0, s, \
+                            a);                                                                 \
+  }
+
 #define RSFDE_LAUNCH_VARIANT(R, L, V)                                                           \
   if (var == V) {                                                                               \
+    const bool mv = a.op <= OP_MV_LAST;                                                         \
     if (strided) {                                                                              \
-      using S = PassShape<R, L, true, V>;                                                       \
-      if (ea) hipExtLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, true>),                      \
-                                    dim3((unsigned)a.nlaunch), dim3(S::NT), 0, s, ea, eb, 0, a); \
-      else hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, true>), dim3((unsigned)a.nlaunch), \
-                              dim3(S::NT), 0, s, a);                                            \
+      if (mv) RSFDE_LAUNCH_ONE(rsfde_pass_kernel, R, L, V, true)                                \
+      else RSFDE_LAUNCH_ONE(rsfde_dst_kernel, R, L, V, true)                                    \
     } else {                                                                                    \
-      using S = PassShape<R, L, false, V>;                                                      \
-      if (ea) hipExtLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, false>),                     \
-                                    dim3((unsigned)a.nlaunch), dim3(S::NT), 0, s, ea, eb, 0, a); \
-      else hipLaunchKernelGGL((rsfde_pass_kernel<R, L, S::F, false>), dim3((unsigned)a.nlaunch), \
-                              dim3(S::NT), 0, s, a);                                            \
+      if (mv) RSFDE_LAUNCH_ONE(rsfde_pass_kernel, R, L, V, false)                               \
+      else RSFDE_LAUNCH_ONE(rsfde_dst_kernel, R, L, V, false)                                   \
     }                                                                                           \
     return hipGetLastError();                                                                   \
+  }
+
+#define RSFDE_LAUNCH_BATCHED_ONE(R, L, V, STR, MODE)                                           \
+  {                                                                                             \
+    using S = PassShape<R, L, STR, V>;                                                          \
+    hipExtLaunchKernelGGL((rsfde_pass_batched<R, L, S::F, STR, MODE>), dim3((unsigned)nblocks), \
+                          dim3(S::NT), 0, s, ea, eb, 0, bl);                                    \
   }
 
 #define RSFDE_LAUNCH_BATCHED_VARIANT(R, L, V)                                                   \
   if (var == V) {                                                                               \
     if (strided) {                                                                              \
-      using S = PassShape<R, L, true, V>;                                                       \
-      hipExtLaunchKernelGGL((rsfde_pass_batched<R, L, S::F, true>), dim3((unsigned)nblocks),    \
-                            dim3(S::NT), 0, s, ea, eb, 0, bl);                                  \
+      if (bl.mv) RSFDE_LAUNCH_BATCHED_ONE(R, L, V, true, PK_MV)                                 \
+      else RSFDE_LAUNCH_BATCHED_ONE(R, L, V, true, PK_TR)                                       \
     } else {                                                                                    \
-      using S = PassShape<R, L, false, V>;                                                      \
-      hipExtLaunchKernelGGL((rsfde_pass_batched<R, L, S::F, false>), dim3((unsigned)nblocks),   \
-                            dim3(S::NT), 0, s, ea, eb, 0, bl);                                  \
+      if (bl.mv) RSFDE_LAUNCH_BATCHED_ONE(R, L, V, false, PK_MV)                                \
+      else RSFDE_LAUNCH_BATCHED_ONE(R, L, V, false, PK_TR)                                      \
     }                                                                                           \
     return hipGetLastError();                                                                   \
   }
