@@ -40,7 +40,7 @@ RSFDE_PLAN(256, 16, 16, 16)
 RSFDE_PLAN(384, 12, 4, 4, 4, 3, 2)
 RSFDE_PLAN(512, 8, 8, 8, 8)
 RSFDE_PLAN(768, 12, 4, 4, 4, 4, 3)
-RSFDE_PLAN(1024, 16, 16, 16, 4)
+RSFDE_PLAN(1024, 8, 8, 8, 8, 2)
 RSFDE_PLAN(1536, 24, 8, 8, 8, 3)
 RSFDE_PLAN(2048, 8, 8, 8, 8, 4)
 RSFDE_PLAN(3072, 24, 8, 8, 8, 3, 2)
@@ -424,4 +424,48 @@ __device__ __forceinline__ void fft_regs(const LdsSeq<R, L> buf, int t, const TW
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) c[m] = v[StageGeom<R, L, NS - 1>::slot(m)];
+}
+
+// Transform from LDS to registers: stages 0 .. NS-2 in LDS, the last stage's
+// results left in c[m] (element t + T m, m < E).  The sequence must be visible
+// to the transform's threads on entry (a barrier taken by the caller).
+template <typename R, int L, int DIR, int S, typename TW>
+__device__ __forceinline__ void fft_lds_stages_to(const LdsSeq<R, L> buf, int t, const TW& tw) {
+  if constexpr (S + 1 < FftPlan<L>::NS) {
+    cpx<R> v[FftPlan<L>::E];
+    stage_read<R, L, S>(buf, t, v);
+    stage_math<R, L, DIR, S>(t, tw, v);
+    stage_sync<L>(false);
+    stage_write<R, L, S>(buf, t, v);
+    stage_sync<L>(false);
+    fft_lds_stages_to<R, L, DIR, S + 1>(buf, t, tw);
+  }
+}
+template <typename R, int L, int DIR, typename TW>
+__device__ __forceinline__ void fft_lds_regs(const LdsSeq<R, L> buf, int t, const TW& tw, cpx<R>* c) {
+  using P = FftPlan<L>;
+  constexpr int E = P::E, NS = P::NS;
+  fft_lds_stages_to<R, L, DIR, 0>(buf, t, tw);
+  cpx<R> v[E];
+  stage_read<R, L, NS - 1>(buf, t, v);
+  stage_math<R, L, DIR, NS - 1>(t, tw, v);
+#pragma unroll
+  for (int m = 0; m < E; ++m) c[m] = v[StageGeom<R, L, NS - 1>::slot(m)];
+}
+
+// Transform from registers (c[m] = element t + T m) to LDS, natural order; the
+// same threads have just read the sequence (fft_lds_regs).  Ends with a
+// workgroup barrier, like fft_lds.
+template <typename R, int L, int DIR, typename TW>
+__device__ __forceinline__ void fft_regs_lds(const LdsSeq<R, L> buf, int t, const TW& tw, const cpx<R>* c) {
+  using P = FftPlan<L>;
+  constexpr int E = P::E, NS = P::NS;
+  cpx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[StageGeom<R, L, 0>::slot(m)] = c[m];
+  stage_math<R, L, DIR, 0>(t, tw, v);
+  stage_sync<L>(false);
+  stage_write<R, L, 0>(buf, t, v);
+  stage_sync<L>(NS == 1);
+  fft_stages<R, L, DIR, 1>(buf, t, tw);
 }

@@ -463,11 +463,16 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
     __syncthreads();
     for (int k = N + t; k < L; k += T) buf[k] = cpx<R>{0, 0};
     __syncthreads();
-    // ---- Toeplitz product by circulant embedding
-    fft_lds<R, L, -1>(buf, t, tw);
-    for (int k = t; k < L; k += T) buf[k] = buf[k] * chat[k];
-    __syncthreads();
-    fft_lds<R, L, +1>(buf, t, tw);
+    // ---- Toeplitz product by circulant embedding; the spectrum multiplies the
+    // forward transform's last-stage results in registers, which feed the
+    // inverse transform's first stage (elements t + T m on both sides)
+    {
+      cpx<R> z[E];
+      fft_lds_regs<R, L, -1>(buf, t, tw, z);
+#pragma unroll
+      for (int m = 0; m < E; ++m) z[m] = z[m] * chat[t + T * m];
+      fft_regs_lds<R, L, +1>(buf, t, tw, z);
+    }
     // ---- combine
     const bool last = op == OP_MV_LAST;
     const bool want_dst = last && (a.flags & (FL_DST_AFTER | FL_PREC_FULL));
