@@ -469,3 +469,26 @@ __device__ __forceinline__ void fft_regs_lds(const LdsSeq<R, L> buf, int t, cons
   stage_sync<L>(NS == 1);
   fft_stages<R, L, DIR, 1>(buf, t, tw);
 }
+
+// Transform of an odd sequence z_{L-n} = -z_n of which only entries 0 .. L/2 are
+// in LDS: the first stage reads x[j + r L/R] for r >= R/2 as -x[(R - r) L/R - j]
+// (first radix even; j = 0, r = R/2 lands on z_{L/2} = 0).  The remaining
+// stages run as in fft_lds; ends with a workgroup barrier.
+template <typename R, int L, int DIR, typename TW>
+__device__ __forceinline__ void fft_lds_odd(const LdsSeq<R, L> buf, int t, const TW& tw) {
+  using G = StageGeom<R, L, 0>;
+  constexpr int RAD = G::RAD, LR = G::LR;
+  static_assert(RAD % 2 == 0, "the first radix must be even");
+  cpx<R> v[FftPlan<L>::E];
+#pragma unroll
+  for (int b = 0; b < G::NB; ++b) {
+    const int j = t + b * G::T;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[b * RAD + r] = r < RAD / 2 ? buf[j + r * LR] : -buf[(RAD - r) * LR - j];
+  }
+  stage_math<R, L, DIR, 0>(t, tw, v);
+  stage_sync<L>(false);
+  stage_write<R, L, 0>(buf, t, v);
+  stage_sync<L>(FftPlan<L>::NS == 1);
+  fft_stages<R, L, DIR, 1>(buf, t, tw);
+}

@@ -551,7 +551,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
     dst_phase = true;
     scale_phase = (a.flags & FL_PREC_FULL) != 0;
     __syncthreads();
-    // ---- odd extension of w for the sine transform
+    // ---- w for the sine transform: entries 0 .. N+1 of its odd extension (the
+    // transform reads the other half mirrored)
     if (t == 0) {
       buf[0] = cpx<R>{0, 0};
       buf[N + 1] = cpx<R>{0, 0};
@@ -560,10 +561,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         const int p = t + i * T;
-        if (p < N) {
-          buf[p + 1] = ra[i];
-          buf[L - 1 - p] = -ra[i];
-        }
+        if (p < N) buf[p + 1] = ra[i];
       }
     } else {
 #pragma unroll
@@ -573,14 +571,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
         if (p < N) {
           LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           set_comp(bb[p + 1], pp & 1, rs[i]);
-          set_comp(bb[L - 1 - p], pp & 1, -rs[i]);
         }
       }
     }
     __syncthreads();
   } else {
     // ---- OP_DST / OP_DSD along a strided axis (the contiguous form returned
-    // above): load the odd extension of the input
+    // above): entries 0 .. N+1 of the odd extension of the input
     if (t == 0) {
       buf[0] = cpx<R>{0, 0};
       buf[N + 1] = cpx<R>{0, 0};
@@ -595,7 +592,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           R x = v ? lc[i] : (R)0;
           LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           set_comp(bb[p + 1], pp & 1, x);
-          set_comp(bb[L - 1 - p], pp & 1, -x);
         }
       }
     }
@@ -605,7 +601,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   // ---- sine transform(s): FFT of the odd extension; for z = x0 + i x1 the
   // transforms are 2 DST(x0) = -Im Z_k, 2 DST(x1) = Re Z_k (k = 1..N).
   (void)dst_phase;
-  fft_lds<R, L, -1>(buf, t, tw);
+  fft_lds_odd<R, L, -1>(buf, t, tw);
   if (scale_phase) {
     // 1/mu_K in the sine basis (eq. Pa, Lemma le:eig, Lemma Heig, eq. q), or a
     // two-sided factor (PM_*); the pass runs along axis 0, the other axes are
@@ -651,13 +647,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         const int p = t + i * T;
-        if (p < N) {
-          buf[p + 1] = ra[i];
-          buf[L - 1 - p] = -ra[i];
-        }
+        if (p < N) buf[p + 1] = ra[i];
       }
       __syncthreads();
-      fft_lds<R, L, -1>(buf, t, tw);
+      fft_lds_odd<R, L, -1>(buf, t, tw);
     }
     // (the host only requests the scaling on the contiguous axis)
   }
