@@ -297,8 +297,10 @@ struct StageGeom {
   static constexpr int slot(int m) { return (m % NB) * RAD + m / NB; }
 };
 
+// (slots r >= rmax are set to zero instead of read)
 template <typename R, int L, int S>
-__device__ __forceinline__ void stage_read(const LdsSeq<R, L> buf, int t, cpx<R>* v) {
+__device__ __forceinline__ void stage_read(const LdsSeq<R, L> buf, int t, cpx<R>* v,
+                                           const int rmax = StageGeom<R, L, S>::RAD) {
   using G = StageGeom<R, L, S>;
   using Q = LdsSeq<R, L>;
   constexpr int BS = Q::BS, LR = G::LR;
@@ -311,7 +313,8 @@ __device__ __forceinline__ void stage_read(const LdsSeq<R, L> buf, int t, cpx<R>
     const int pj = Q::pos(j);
 #pragma unroll
     for (int r = 0; r < G::RAD; ++r)
-      v[b * G::RAD + r] = rd_fold ? buf.p[pj + r * (LR + LR / BS)] : buf[j + r * LR];
+      v[b * G::RAD + r] = r >= rmax ? cpx<R>{0, 0}
+                                    : (rd_fold ? buf.p[pj + r * (LR + LR / BS)] : buf[j + r * LR]);
   }
 }
 
@@ -441,14 +444,25 @@ __device__ __forceinline__ void fft_lds_stages_to(const LdsSeq<R, L> buf, int t,
     fft_lds_stages_to<R, L, DIR, S + 1>(buf, t, tw);
   }
 }
-template <typename R, int L, int DIR, typename TW>
+// ZU: entries L/2 .. L-1 of the sequence are zero and not read (the first
+// stage takes zeros for r >= R/2, first radix even).
+template <typename R, int L, int DIR, bool ZU = false, typename TW>
 __device__ __forceinline__ void fft_lds_regs(const LdsSeq<R, L> buf, int t, const TW& tw, cpx<R>* c) {
   using P = FftPlan<L>;
+  using G = StageGeom<R, L, 0>;
   constexpr int E = P::E, NS = P::NS;
-  fft_lds_stages_to<R, L, DIR, 0>(buf, t, tw);
+  static_assert(!ZU || G::RAD % 2 == 0, "the first radix must be even");
   cpx<R> v[E];
-  stage_read<R, L, NS - 1>(buf, t, v);
-  stage_math<R, L, DIR, NS - 1>(t, tw, v);
+  stage_read<R, L, 0>(buf, t, v, ZU ? G::RAD / 2 : G::RAD);
+  stage_math<R, L, DIR, 0>(t, tw, v);
+  if constexpr (NS > 1) {
+    stage_sync<L>(false);
+    stage_write<R, L, 0>(buf, t, v);
+    stage_sync<L>(false);
+    fft_lds_stages_to<R, L, DIR, 1>(buf, t, tw);
+    stage_read<R, L, NS - 1>(buf, t, v);
+    stage_math<R, L, DIR, NS - 1>(t, tw, v);
+  }
 #pragma unroll
   for (int m = 0; m < E; ++m) c[m] = v[StageGeom<R, L, NS - 1>::slot(m)];
 }

@@ -461,18 +461,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
       }
     }
     __syncthreads();
-    for (int k = N + t; k < L; k += T) buf[k] = cpx<R>{0, 0};
-    __syncthreads();
-    // ---- Toeplitz product by circulant embedding; the spectrum multiplies the
-    // forward transform's last-stage results in registers, which feed the
-    // inverse transform's first stage (elements t + T m on both sides)
-    {
-      cpx<R> z[E];
-      fft_lds_regs<R, L, -1>(buf, t, tw, z);
+    // ---- Toeplitz product by circulant embedding.  The zero padding is not
+    // stored: entry N is zero and the first stage takes entries L/2 .. L-1 as
+    // zeros.  The spectrum multiplies the forward transform's last-stage results
+    // in registers, which feed the inverse transform's first stage (elements
+    // t + T m on both sides); on the contiguous axis the inverse transform's
+    // results stay in registers for the combine below.
+    cpx<R> z[E];
+    fft_lds_regs<R, L, -1, true>(buf, t, tw, z);
 #pragma unroll
-      for (int m = 0; m < E; ++m) z[m] = z[m] * chat[t + T * m];
-      fft_regs_lds<R, L, +1>(buf, t, tw, z);
-    }
+    for (int m = 0; m < E; ++m) z[m] = z[m] * chat[t + T * m];
+    if constexpr (STRIDED) fft_regs_lds<R, L, +1>(buf, t, tw, z);
+    else fft_regs<R, L, +1, false>(buf, t, tw, z);
     // ---- combine
     const bool last = op == OP_MV_LAST;
     const bool want_dst = last && (a.flags & (FL_DST_AFTER | FL_PREC_FULL));
@@ -507,7 +507,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
       for (int i = 0; i < NE; ++i) {
         const int p = t + i * T;
         if (p < N) {
-          cpx<R> w = ra[i] + buf[p] * eta;
+          cpx<R> w = ra[i] + z[i] * eta;  // z[i]: element p of T c
           if (last) {
             w = w * gam;
             if (xin) {
