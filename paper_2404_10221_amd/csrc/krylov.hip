@@ -243,7 +243,9 @@ __device__ __forceinline__ void sub_cols(T& wi, T (&vk)[KEEP ? KM : 1], const T*
     }
 }
 
-// ---- CGS2 sweep 2: h = Vbar^T w / |v| ; w -= V h ; partials of Vbar^T w ------------------
+// ---- CGS2 sweep 2: h = Vbar^T w / |v| ; partials of Vbar^T (w - V h) ----------------------
+// (w - V h is formed per row for the dot products and not stored: sweep 3 takes
+// w - V (h + h2) from the unmodified w)
 template <int KM>
 __device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk) {
   constexpr int NT = SweepNT<2, KM>::value;
@@ -264,17 +266,16 @@ __device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk)
   double acc[KM];
 #pragma unroll
   for (int k = 0; k < KM; ++k) acc[k] = 0.0;
-  double* __restrict__ w = a.w;
+  const double* __restrict__ w = a.w;
   const double* __restrict__ V = a.V;
   const int64_t stride = (int64_t)nblk * NT;
   const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
-  double2* __restrict__ w2 = (double2*)w;
+  const double2* __restrict__ w2 = (const double2*)w;
   const double2* __restrict__ V2 = (const double2*)V;
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
     double2 wi = w2[i];
     double2 vk[KEEP ? KM : 1];
     sub_cols<KM, KEEP>(wi, vk, V2, ld2, i, cf, nv);
-    w2[i] = wi;
 #pragma unroll
     for (int kb = 0; kb < KM; kb += CH)
       if (kb < nv) {
@@ -295,7 +296,6 @@ __device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk)
     double wi = w[i];
     double vk[1];
     sub_cols<KM, false>(wi, vk, V, a.ldv, i, cf, nv);
-    w[i] = wi;
 #pragma unroll
     for (int kb = 0; kb < KM; kb += CH)
       if (kb < nv) {
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__((SweepNT<2, KM>::value)) k_sweep2(const KryArg
   sweep2_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
-// ---- CGS2 sweep 3: h2 = Vbar^T w / |v| ; w -= V h2 ; partials of ||w||^2 -----------------
+// ---- CGS2 sweep 3: h2 = Vbar^T (w - V h) / |v| ; w -= V (h + h2) ; partials of ||w||^2 ---
 template <int KM>
 __device__ __forceinline__ void sweep3_body(const KryArgs& a, int bid, int nblk) {
   constexpr int NT = SweepNT<3, KM>::value;
@@ -329,7 +329,7 @@ __device__ __forceinline__ void sweep3_body(const KryArgs& a, int bid, int nblk)
     const double sc = st->vsc[threadIdx.x];
     const double h2 = cf[threadIdx.x] * sc;
     if (bid == 0) st->h2[threadIdx.x] = h2;
-    cf[threadIdx.x] = h2 * sc;
+    cf[threadIdx.x] = (st->h[threadIdx.x] + h2) * sc;  // both projections from the original w
   }
   __syncthreads();
   double acc[1] = {0.0};
