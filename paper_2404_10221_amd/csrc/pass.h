@@ -186,10 +186,25 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   const int64_t inner = a.inner;
 
   // element (slot i) -> position p, pencil-in-tile pp (strided) ; validity
+  // Strided slots: lanes run over the tile's pencils (coalesced row segments).
+  // The sine-transform kernel spreads a thread's slots along the pencil
+  // (position tid/PT + i NT/PT); the operator kernel gives each thread a run of
+  // NE consecutive positions of one pencil, so its B stencils need only the
+  // run's two neighbours besides the run itself.
+  // Runs need an even T (T/2 threads per pencil); they are used where they
+  // measured faster, for transforms of one wavefront (T = 64: 3-D 255^3 axis-2
+  // operator pass 18 % faster), and not at T = 128 (3-D 511^3, 9 % slower) or
+  // T = 256 (2-D 1023^2, no change).
+  constexpr bool runs = STRIDED && mv_op && T == 64;
   auto s_pos = [&](int i, int& p, int& pp) {
-    const int flat = tid + i * NT;
-    p = flat / PT;
-    pp = flat - p * PT;
+    if constexpr (runs) {
+      pp = tid % PT;
+      p = (tid / PT) * NE + i;
+    } else {
+      const int flat = tid + i * NT;
+      p = flat / PT;
+      pp = flat - p * PT;
+    }
   };
   auto c_row = [&](int comp) -> int64_t { return row0 + 2 * f + comp; };
 
@@ -207,6 +222,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   // the mirrored x_{N-p}, p = t + T i < L/2.
   constexpr int NL = STRIDED ? NE : 2 * NE;  // values per input array per thread
   R lc[NL], la[NL];
+  R nbc[2], nba[2];  // strided operator passes: the run's neighbours
+  (void)nbc;
+  (void)nba;
   {
     const bool ld_a = mv_op;
     if constexpr (!STRIDED) {
@@ -237,6 +255,17 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
         const int64_t g = gbase + (int64_t)(p < N ? p : 0) * inner + (pp < nvalid ? pp : 0);
         lc[i] = ld_any<R>(a.in_c, g, in64);
         if (ld_a) la[i] = ld_any<R>(a.in_a, g, false);
+      }
+      if constexpr (runs) {
+        // the run's neighbours p0 - 1 and p0 + NE (clamped; zero outside [0, N))
+        const int pp = tid % PT, p0 = (tid / PT) * NE;
+        const int64_t col = pp < nvalid ? pp : 0;
+        const int64_t gm = gbase + (int64_t)(p0 >= 1 ? p0 - 1 : 0) * inner + col;
+        const int64_t gq = gbase + (int64_t)(p0 + NE < N ? p0 + NE : 0) * inner + col;
+        nbc[0] = ld_any<R>(a.in_c, gm, in64);
+        nbc[1] = ld_any<R>(a.in_c, gq, in64);
+        nba[0] = ld_any<R>(a.in_a, gm, false);
+        nba[1] = ld_any<R>(a.in_a, gq, false);
       }
     }
   }
@@ -385,7 +414,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
 
   if (is_mv) {
     const bool ev_mode = op == OP_MV_FIRST || (a.flags & FL_FIRST_IS_LAST);
-    // ---- load: Toeplitz input c into slots [0,N), stencil input into [N+1, 2N+1)
+    // ---- load (contiguous axis): Toeplitz input c into slots [0,N), stencil
+    // input into [N+1, 2N+1); entry N stays zero (the Toeplitz input's padding)
     if (t == 0) {
       buf[N] = cpx<R>{0, 0};
       buf[2 * N + 1] = cpx<R>{0, 0};
@@ -408,7 +438,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           buf[N + 1 + p] = cpx<R>{a0, a1};
         }
       }
-    } else {
+    } else if constexpr (!runs) {
+      // (strided, one thread per transform) c and the stencil input into LDS
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         int p, pp;
@@ -423,11 +454,44 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           set_comp(bb[N + 1 + p], pp & 1, av);
         }
       }
+    } else {
+      // ---- the thread's run p0 .. p0+NE-1 of pencil pp with its two neighbours
+      // (zero outside [0, N)): c into LDS for the Toeplitz product; both stencils
+      // in registers
+      const int pp = tid % PT, p0 = (tid / PT) * NE;
+      const bool v = pp < nvalid;
+      const bool store_c = op != OP_MV_LAST;
+      R cr[NE + 2], ar[NE + 2];
+      cr[0] = v && p0 >= 1 ? nbc[0] * sc : (R)0;
+      ar[0] = v && p0 >= 1 ? nba[0] : (R)0;
+      cr[NE + 1] = v && p0 + NE < N ? nbc[1] * sc : (R)0;
+      ar[NE + 1] = v && p0 + NE < N ? nba[1] : (R)0;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const bool in = v && p0 + i < N;
+        cr[i + 1] = in ? lc[i] * sc : (R)0;
+        ar[i + 1] = in ? la[i] : (R)0;
+      }
+      if (ev_mode) {
+#pragma unroll
+        for (int k = 0; k < NE + 2; ++k) ar[k] *= cr[k];
+      }
+      const LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int p = p0 + i;
+        if (p < N) {
+          set_comp(bb[p], pp & 1, cr[i + 1]);
+          const R bc = cr[i + 1] * bd + (cr[i] + cr[i + 2]) * bo;
+          rs[i] = ar[i + 1] * bd + (ar[i] + ar[i + 2]) * bo;
+          if (store_c && v) st_any<R>(a.out_c, gbase + (int64_t)p * inner + pp, bc, false);
+        }
+      }
     }
     __syncthreads();
-    // ---- stencils: keep B a in registers, store c_out = B c
-    const bool store_c = op != OP_MV_LAST;
     if constexpr (!STRIDED) {
+      // ---- stencils: keep B a in registers, store c_out = B c
+      const bool store_c = op != OP_MV_LAST;
       const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
       const int64_t b0 = c_row(0) * N, b1 = c_row(1) * N;
 #pragma unroll
@@ -444,7 +508,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           }
         }
       }
-    } else {
+      __syncthreads();
+    } else if constexpr (!runs) {
+      const bool store_c = op != OP_MV_LAST;
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         int p, pp;
@@ -459,8 +525,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           if (store_c && pp < nvalid) st_any<R>(a.out_c, gbase + (int64_t)p * inner + pp, bc, false);
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
     // ---- Toeplitz product by circulant embedding.  The zero padding is not
     // stored: entry N is zero and the first stage takes entries L/2 .. L-1 as
     // zeros.  The spectrum multiplies the forward transform's last-stage results
