@@ -45,7 +45,7 @@ __device__ __forceinline__ unsigned split_u32(unsigned r, unsigned n, double inv
   return q;
 }
 
-// Time factors of the field families, evaluated once per workgroup.
+// Time factors of the field families, evaluated once per launch on the host.
 struct TimeF {
   double cos_t, exp_mt;
 };

@@ -60,14 +60,6 @@ __device__ __forceinline__ double e_value(const FieldDev& E, int d, const double
   }
 }
 
-// cos t and exp(-t) by one thread of the workgroup (every thread reaches the barrier)
-__device__ __forceinline__ TimeF time_factors(double t) {
-  __shared__ TimeF tfs;
-  if (threadIdx.x == 0) tfs = TimeF{cos(t), exp(-t)};
-  __syncthreads();
-  return tfs;
-}
-
 __device__ __forceinline__ double poly_p(double x, int a) {
   const double b = x * (1.0 - x);
   double p = 1.0;
@@ -144,25 +136,28 @@ __device__ __forceinline__ void fields_eval_at(const FieldDev& E, const FieldDev
 
 __global__ void __launch_bounds__(256)
 k_fields_eval(const FieldDev E, const FieldDev F, int which, const GridDev g, double t,
-              double* __restrict__ out) {
-  const TimeF tf = time_factors(t);
+              const TimeF tf, double* __restrict__ out) {
   fields_eval_at(E, F, which, g, t, tf, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // one launch for many instances: job[s] covers blocks start[s] .. start[s+1)
 __global__ void __launch_bounds__(256)
-k_fields_eval_b(const FieldJob* __restrict__ jobs, const int* __restrict__ start, int n, double t) {
+k_fields_eval_b(const FieldJob* __restrict__ jobs, const int* __restrict__ start, int n, double t,
+                const TimeF tf) {
   const int slot = batch_slot(start, n, blockIdx.x);
   const FieldJob& J = jobs[slot];
-  const TimeF tf = time_factors(t);
   fields_eval_at(J.e, J.f, J.which, J.g, t, tf, J.out,
                  (int64_t)((int)blockIdx.x - start[slot]) * blockDim.x + threadIdx.x);
 }
 
+// cos t and exp(-t), once per launch on the host
+static TimeF time_factors(double t) { return TimeF{cos(t), exp(-t)}; }
+
 hipError_t fields_eval_batched(const FieldJob* jobs, const int* start, int n, int64_t nblocks,
                                double t, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fields_eval_b, dim3((unsigned)nblocks), dim3(256), 0, s, jobs, start, n, t);
+  hipLaunchKernelGGL(k_fields_eval_b, dim3((unsigned)nblocks), dim3(256), 0, s, jobs, start, n, t,
+                     time_factors(t));
   return hipGetLastError();
 }
 
@@ -170,7 +165,7 @@ hipError_t fields_eval(const FieldDev& e, const FieldDev& f, int which, const Gr
                        double* out, hipStream_t s) {
   if (g.size == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fields_eval, dim3((unsigned)((g.size + 255) / 256)), dim3(256), 0, s, e, f,
-                     which, g, t, out);
+                     which, g, t, time_factors(t), out);
   return hipGetLastError();
 }
 
