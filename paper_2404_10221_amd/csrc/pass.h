@@ -346,8 +346,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
 
   const int op = a.op;
   const bool is_mv = mv_op;
-  bool dst_phase = !is_mv;          // a sine transform follows
-  bool scale_phase = is_dsd;        // and a 1/mu scaling + second transform
+  bool scale_phase = is_dsd;  // a 1/mu scaling + second sine transform follow the first
 
   if constexpr (!STRIDED && !mv_op) {
     // ---- register-staged sine transforms along a contiguous axis.  Thread t
@@ -614,7 +613,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
       }
     }
     if (!want_dst) return;  // uniform across the workgroup
-    dst_phase = true;
     scale_phase = (a.flags & FL_PREC_FULL) != 0;
     __syncthreads();
     // ---- w for the sine transform: entries 0 .. N+1 of its odd extension (the
@@ -666,7 +664,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
 
   // ---- sine transform(s): FFT of the odd extension; for z = x0 + i x1 the
   // transforms are 2 DST(x0) = -Im Z_k, 2 DST(x1) = Re Z_k (k = 1..N).
-  (void)dst_phase;
   fft_lds_odd<R, L, -1>(buf, t, tw);
   if (scale_phase) {
     // 1/mu_K in the sine basis (eq. Pa, Lemma le:eig, Lemma Heig, eq. q), or a
