@@ -48,7 +48,10 @@ def _check(inst, max_iter_diff=None, **over):
 
 
 @pytest.mark.parametrize("d,n", [(1, (3,)), (2, (3, 5)), (3, (3, 3, 5)), (1, (2047,)), (1, (1535,)),
-                                 (2, (2047, 7)), (2, (5, 1535))])
+                                 (2, (2047, 7)), (2, (5, 1535)),
+                                 # strided axes with 64-thread transforms (L = 512, 768): the
+                                 # operator pass's per-thread runs, beside a one-thread axis (L = 12)
+                                 (2, (5, 255)), (2, (3, 383)), (3, (3, 255, 5))])
 def test_smallest_and_largest_transform_lengths(d, n):
     say(f"[edges] d={d} n={n}")
     status, _, _ = _check(_inst(d, n))
