@@ -96,13 +96,21 @@ typedef struct {
                            then rsfde_set_ebar must be called, or rsfde_solve pre-scans e */
   int     restart;      /* GMRES restart length m, 1..64 */
   double  rtol;         /* relative tolerance on the preconditioned residual, > 0 */
-  int     max_cycles;   /* restarts allowed per step (per inner solve in the mixed form), >= 1 */
+  int     max_cycles;   /* GMRES cycles allowed per step, >= 1 (RSFDE_FP64; the mixed form
+                           runs one FP32 cycle per refinement sweep and is bounded by
+                           max_outer alone) */
   int     precision;    /* RSFDE_FP64 or RSFDE_MIXED */
   int     x0_mode;      /* 0: GMRES starts from u^{(m)}; 1: from zero */
-  double  inner_rtol;   /* RSFDE_MIXED: tolerance of each FP32 inner solve (0 -> 1e-5) */
+  double  inner_rtol;   /* RSFDE_MIXED: tolerance of each FP32 inner solve relative to its
+                           starting residual (0 -> sqrt(outer bound), clamped to
+                           [1e-6, 1e-3], so that two sweeps reach the outer bound) */
   int     max_outer;    /* RSFDE_MIXED: refinement sweeps allowed per step (0 -> 30) */
   int     method;       /* RSFDE_OPGM (0), RSFDE_TPGM or RSFDE_SPGM; the last two with
                            RSFDE_MIXED are RSFDE_E_UNSUPPORTED */
+  double  outer_rtol;   /* RSFDE_MIXED: refinement stops once the FP64 preconditioned true
+                           residual satisfies ||z|| <= outer_rtol ||z_0|| (0 -> rtol / 10,
+                           so that the refined solution stays within rounding of the FP64
+                           solve's); must not exceed rtol.  Ignored by RSFDE_FP64 */
 } rsfde_params;
 
 /* Per-instance result of one step (summed over the steps of rsfde_solve). */
@@ -112,7 +120,14 @@ typedef struct {
   int    outer_sweeps;  /* refinement sweeps (mixed form), else 0 */
   int    converged;     /* 1 when the stopping rule was met */
   double beta0;         /* ||z_0||_2 of the (last) step */
-  double rel_pres;      /* final preconditioned residual / beta0 of the (last) step */
+  double rel_pres;      /* final preconditioned residual / beta0 of the (last) step: the
+                           GMRES estimate |g_{k+1}| (RSFDE_FP64) or the recomputed FP64
+                           residual of the last refinement sweep (RSFDE_MIXED) */
+  double rel_true_res;  /* ||M (b - A u^{(m+1)})||_2 / beta0 of the (last) step, recomputed
+                           in FP64 from the returned u with the stopping rule's
+                           preconditioner M; computed by the mixed form's last sweep, and
+                           in the other forms only while rsfde_set_true_residual is on
+                           (else -1) */
 } rsfde_stats;
 
 /* Analytic field families the library can evaluate on the device (synthetic
@@ -251,6 +266,13 @@ int rsfde_get_tables(rsfde_handle h, int instance, int axis, double* s, double* 
  * t_{m+1/2} = (m + 1/2) dt and set ebar from its extremes (eq. dhat, eq. bard).
  * Time-independent fields are sampled once. */
 int rsfde_prescan_ebar(rsfde_handle h, int instance, int M);
+
+/* True-residual check (enable = 1; default 0): every step of the FP64 forms ends
+ * with one more residual evaluation in FP64, z = M (b - A u^{(m+1)}) with the
+ * stopping rule's preconditioner M (Section 4), and reports ||z|| / ||z_0|| as
+ * rsfde_stats.rel_true_res.  It costs about one Arnoldi iteration per step and
+ * changes no result.  The mixed form always reports it.  Errors: RSFDE_E_INVALID_ARG. */
+int rsfde_set_true_residual(rsfde_handle h, int enable);
 
 /* Graph replay (enable = 1) or direct launches (0, the default) for the Arnoldi
  * steps.  With replay on, each step's launch sequence (operator chain and the

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -290,6 +291,7 @@ struct rsfde_ctx {
     int fp, ax, cls, L, var;
   };
   std::vector<AtEntry> atc;  // batched handles: one tile variant per (precision, axis, class, L)
+  bool true_res = false;                 // rsfde_set_true_residual
   hipStream_t stream = nullptr;
   GmresSummary* pinned = nullptr;
   unsigned tmask = 0;
@@ -353,6 +355,7 @@ static int validate(const rsfde_params* p) {
   if (p->x0_mode != 0 && p->x0_mode != 1) return RSFDE_E_INVALID_ARG;
   if (!(p->inner_rtol >= 0.0 && p->inner_rtol < 1.0)) return RSFDE_E_INVALID_ARG;
   if (p->max_outer < 0) return RSFDE_E_INVALID_ARG;
+  if (!(p->outer_rtol >= 0.0 && p->outer_rtol <= p->rtol)) return RSFDE_E_INVALID_ARG;
   if (p->method != RSFDE_OPGM && p->method != RSFDE_TPGM && p->method != RSFDE_SPGM)
     return RSFDE_E_INVALID_ARG;
   if (p->method != RSFDE_OPGM && p->precision != RSFDE_FP64) return RSFDE_E_UNSUPPORTED;
@@ -977,6 +980,22 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
   }
 }
 
+// Bound on the FP64 preconditioned true residual that ends the mixed form's
+// refinement, relative to ||z_0||: a tenth of rtol unless set.  Two solutions
+// that both meet rtol may differ by about cond * rtol; refining a decade further
+// keeps the refined solution well inside the FP64 solve's own distance from the
+// exact solution of the step's system.
+static double outer_tol(const rsfde_params& p) { return p.outer_rtol > 0.0 ? p.outer_rtol : 0.1 * p.rtol; }
+
+// Tolerance of each FP32 inner solve of the mixed form, relative to its start:
+// unless set, the square root of the outer bound (two refinement sweeps reach
+// it), kept within [1e-6, 1e-3] (below 1e-6 the FP32 operator's rounding, not
+// the inner tolerance, limits what a sweep gains).
+static double inner_tol(const rsfde_params& p) {
+  if (p.inner_rtol > 0.0) return p.inner_rtol;
+  return std::min(1e-3, std::max(1e-6, std::sqrt(outer_tol(p))));
+}
+
 static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f_half, double* u,
                     rsfde_stats* stats) {
   if (!I.ebar_set) return RSFDE_E_STATE;
@@ -995,14 +1014,16 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
   memset(&st, 0, sizeof(st));
   GmresSummary S;
   memset(&S, 0, sizeof(S));
-  const double inner_rtol = p.inner_rtol > 0.0 ? p.inner_rtol : 1e-5;
+  const double inner_rtol = inner_tol(p);
+  const double stop_rtol = mixed ? outer_tol(p) : p.rtol;
   const int max_outer = p.max_outer > 0 ? p.max_outer : 30;
   const int max_loops = mixed ? max_outer + 1 : p.max_cycles;
   int status = RSFDE_W_NOT_CONVERGED;
+  double true_res = -1.0;
   for (int cyc = 0; cyc < max_loops; ++cyc) {
     // z = (BP)^{-1} (b - A u) in FP64 into V_0
     CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
-    CK(kry_cycle_init(I.V, I.n, I.st, I.partial, cyc == 0 ? 1 : 0, p.rtol, inner_rtol,
+    CK(kry_cycle_init(I.V, I.n, I.st, I.partial, cyc == 0 ? 1 : 0, stop_rtol, inner_rtol,
                       mixed ? 1 : 0, p.restart, h->stream));
     if (mixed && cyc == max_outer) {
       // final check only
@@ -1018,17 +1039,29 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
       I.k_prev = S.k;
     }
     if (mixed) {
+      // the cycle start just run found the FP64 residual below the bound
       if (S.k == 0 && S.flag == GM_CONVERGED) {
         status = RSFDE_OK;
         break;
       }
       st.outer_sweeps += 1;
-    } else {
-      if (S.flag == GM_CONVERGED || S.flag == GM_BREAKDOWN) {
-        status = RSFDE_OK;
-        break;
-      }
+    } else if (S.flag == GM_CONVERGED) {
+      status = RSFDE_OK;
+      break;
     }
+    // a full cycle or a (near-)breakdown: the next cycle start recomputes the
+    // residual and decides
+  }
+  if (mixed) {
+    true_res = S.beta0 > 0 ? S.beta / S.beta0 : 0.0;
+  } else if (h->true_res) {
+    // recompute z = M (b - A u) in FP64 from the returned u (V_0 is free here)
+    CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
+    CK(kry_cycle_init(I.V, I.n, I.st, I.partial, 0, p.rtol, inner_rtol, 0, p.restart, h->stream));
+    GmresSummary R;
+    CKS(read_summary(h, I, &R));
+    if (!std::isfinite(R.beta)) return RSFDE_E_NONFINITE;
+    true_res = R.beta0 > 0 ? R.beta / R.beta0 : 0.0;
   }
   if (stats) {
     stats->iters += st.iters;
@@ -1037,6 +1070,7 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
     stats->converged = status == RSFDE_OK ? 1 : 0;
     stats->beta0 = S.beta0;
     stats->rel_pres = S.beta0 > 0 ? (mixed ? S.beta : S.res) / S.beta0 : 0.0;
+    stats->rel_true_res = true_res;
   }
   return status;
 }
@@ -1206,8 +1240,8 @@ static int plan_krylov(rsfde_ctx* h, int r, const std::vector<int>& S, double* c
     d.k.m = I.p.restart;
     d.x = u[i];
     d.partial = I.partial;
-    d.rtol = I.p.rtol;
-    d.inner_rtol = I.p.inner_rtol > 0.0 ? I.p.inner_rtol : 1e-5;
+    d.rtol = I.p.precision == RSFDE_MIXED ? outer_tol(I.p) : I.p.rtol;
+    d.inner_rtol = inner_tol(I.p);
     d.nb = kry_blocks(I.n);
     d.nbu = upd_blocks(I.n);
     d.mixed = I.p.precision == RSFDE_MIXED ? 1 : 0;
@@ -1476,7 +1510,9 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
           st[i].outer_sweeps += 1;
         }
       } else {
-        if (S.flag == GM_CONVERGED || S.flag == GM_BREAKDOWN) {
+        // a full cycle or a (near-)breakdown starts a new cycle, whose start
+        // recomputes the residual and decides
+        if (S.flag == GM_CONVERGED) {
           status[i] = RSFDE_OK;
           done = true;
         } else if (cyc + 1 >= I.p.max_cycles) {
@@ -1486,6 +1522,22 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
       if (!done) next.push_back(i);
     }
     act = next;
+  }
+  std::vector<double> true_res(C, -1.0);
+  for (int i = 0; i < C; ++i) {
+    if (mixed) {
+      true_res[i] = last[i].beta0 > 0 ? last[i].beta / last[i].beta0 : 0.0;
+    } else if (h->true_res) {
+      // the recomputed FP64 residual of each instance, one at a time (V_0 is free)
+      Inst& I = h->inst[i];
+      CKS(run_chain(h, I, CH_RESID, false, u[i], nullptr, I.b, 1.0, I.V));
+      CK(kry_cycle_init(I.V, I.n, I.st, I.partial, 0, I.p.rtol, inner_tol(I.p), 0, I.p.restart,
+                        h->stream));
+      GmresSummary R;
+      CKS(read_summary(h, I, &R));
+      if (!std::isfinite(R.beta)) return RSFDE_E_NONFINITE;
+      true_res[i] = R.beta0 > 0 ? R.beta / R.beta0 : 0.0;
+    }
   }
   int worst = RSFDE_OK;
   for (int i = 0; i < C; ++i) {
@@ -1497,6 +1549,7 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
       o.converged = status[i] == RSFDE_OK ? 1 : 0;
       o.beta0 = last[i].beta0;
       o.rel_pres = last[i].beta0 > 0 ? (mixed ? last[i].beta : last[i].res) / last[i].beta0 : 0.0;
+      o.rel_true_res = true_res[i];
     }
     worst = std::max(worst, status[i]);
   }
@@ -1827,6 +1880,7 @@ int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx, double
           stats[i].converged = (m == 0 ? 1 : stats[i].converged) & sb[i].converged;
           stats[i].beta0 = sb[i].beta0;
           stats[i].rel_pres = sb[i].rel_pres;
+          stats[i].rel_true_res = sb[i].rel_true_res;
         }
       continue;
     }
@@ -1850,6 +1904,7 @@ int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx, double
         stats[i].converged = (m == 0 ? 1 : stats[i].converged) & s1.converged;
         stats[i].beta0 = s1.beta0;
         stats[i].rel_pres = s1.rel_pres;
+        stats[i].rel_true_res = s1.rel_true_res;
       }
     }
   }
@@ -2124,6 +2179,12 @@ int rsfde_set_graph(rsfde_handle h, int enable) {
     graphs_clear(h->bgexec);
   }
   h->graphs = enable != 0;
+  return RSFDE_OK;
+}
+
+int rsfde_set_true_residual(rsfde_handle h, int enable) {
+  if (!h || (enable != 0 && enable != 1)) return RSFDE_E_INVALID_ARG;
+  h->true_res = enable != 0;
   return RSFDE_OK;
 }
 

@@ -40,7 +40,7 @@ EXPORTED = (
     "rsfde_destroy", "rsfde_strerror", "rsfde_set_fields", "rsfde_eval_field",
     "rsfde_eval_field_batch", "rsfde_set_graph", "rsfde_apply_A",
     "rsfde_apply_prec", "rsfde_apply_prec_form", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
-    "rsfde_get_timing", "rsfde_prescan_ebar", "rsfde_get_pass_shape",
+    "rsfde_get_timing", "rsfde_prescan_ebar", "rsfde_get_pass_shape", "rsfde_set_true_residual",
 )
 
 K_CLASSES = ("mv_first", "mv_mid", "mv_last", "dst", "dsd", "dots", "orth_dots", "orth_norm", "update")
@@ -53,13 +53,14 @@ class rsfde_params(C.Structure):
         ("e_min", C.c_double), ("e_max", C.c_double), ("restart", C.c_int), ("rtol", C.c_double),
         ("max_cycles", C.c_int), ("precision", C.c_int), ("x0_mode", C.c_int),
         ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("method", C.c_int),
+        ("outer_rtol", C.c_double),
     ]
 
 
 class rsfde_stats(C.Structure):
     _fields_ = [
         ("iters", C.c_int), ("cycles", C.c_int), ("outer_sweeps", C.c_int), ("converged", C.c_int),
-        ("beta0", C.c_double), ("rel_pres", C.c_double),
+        ("beta0", C.c_double), ("rel_pres", C.c_double), ("rel_true_res", C.c_double),
     ]
 
     def as_dict(self):
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_get_tables.argtypes = [P, I, I, P, P, P]
     lib.rsfde_set_timing.argtypes = [P, C.c_uint, I]
     lib.rsfde_set_graph.argtypes = [P, I]
+    lib.rsfde_set_true_residual.argtypes = [P, I]
     lib.rsfde_get_timing.argtypes = [P, I, C.POINTER(C.c_longlong), C.POINTER(D), C.POINTER(D)]
     lib.rsfde_prescan_ebar.argtypes = [P, I, I]
     lib.rsfde_get_pass_shape.argtypes = [P, I, I, I, I, C.POINTER(I), C.POINTER(I)]
@@ -148,7 +150,7 @@ def _stream(stream=None) -> int:
 
 def make_params(d, n, alpha, kappa, dt, *, lo=None, hi=None, e_min=0.0, e_max=0.0, restart=20,
                 rtol=1e-10, max_cycles=10, precision=RSFDE_FP64, x0_mode=0, inner_rtol=0.0,
-                max_outer=0, method=0) -> rsfde_params:
+                max_outer=0, method=0, outer_rtol=0.0) -> rsfde_params:
     p = rsfde_params()
     p.d = int(d)
     for i in range(3):
@@ -163,6 +165,7 @@ def make_params(d, n, alpha, kappa, dt, *, lo=None, hi=None, e_min=0.0, e_max=0.
     p.precision, p.x0_mode = int(precision), int(x0_mode)
     p.inner_rtol, p.max_outer = float(inner_rtol), int(max_outer)
     p.method = int(method)
+    p.outer_rtol = float(outer_rtol)
     return p
 
 
@@ -295,6 +298,10 @@ def rsfde_get_pass_shape(h, instance: int, axis: int, precision: int, transform:
 
 def rsfde_set_graph(h, enable: bool) -> None:
     _check(load_library().rsfde_set_graph(h, 1 if enable else 0), "rsfde_set_graph")
+
+
+def rsfde_set_true_residual(h, enable: bool) -> None:
+    _check(load_library().rsfde_set_true_residual(h, 1 if enable else 0), "rsfde_set_true_residual")
 
 
 def rsfde_set_timing(h, mask: int, every: int = 1) -> None:

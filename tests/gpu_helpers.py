@@ -46,3 +46,15 @@ def solver_for(inst, ebar=None, **over):
 
 def oracle_problem(inst):
     return O.OracleProblem(inst)
+
+
+# Tolerance of the oracle's "tight" solves: the reference a solver form is held to
+# when it reaches the stopping bound along another Krylov sequence than the
+# oracle's FP64 GMRES (the mixed form), so that the comparison measures that form's
+# own error and not the oracle's distance cond * rtol from the exact solution.
+TIGHT_RTOL = 1e-13
+
+
+def tight(inst):
+    from dataclasses import replace
+    return replace(inst, rtol=TIGHT_RTOL, max_cycles=max(inst.max_cycles, 20))

@@ -64,6 +64,8 @@ def _base(**over):
     (dict(precision=2), R.RSFDE_E_INVALID_ARG),
     (dict(x0_mode=3), R.RSFDE_E_INVALID_ARG),
     (dict(method=3), R.RSFDE_E_INVALID_ARG),
+    (dict(precision=R.RSFDE_MIXED, rtol=1e-10, outer_rtol=1e-9), R.RSFDE_E_INVALID_ARG),
+    (dict(precision=R.RSFDE_MIXED, outer_rtol=-1e-12), R.RSFDE_E_INVALID_ARG),
     (dict(method=R.RSFDE_SPGM, precision=R.RSFDE_MIXED), R.RSFDE_E_UNSUPPORTED),
     (dict(method=R.RSFDE_TPGM, precision=R.RSFDE_MIXED), R.RSFDE_E_UNSUPPORTED),
     (dict(lo=(0.0, 1.0), hi=(1.0, 1.0)), R.RSFDE_E_INVALID_ARG),
@@ -107,6 +109,7 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.rsfde_apply_A(None, 0, None, None, None) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_set_timing(None, 1, 1) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_set_graph(None, 1) == R.RSFDE_E_INVALID_ARG
+    assert lib.rsfde_set_true_residual(None, 1) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_apply_prec_form(None, 0, 1, None, None) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_get_pass_shape(None, 0, 0, 0, 0, None, None) == R.RSFDE_E_INVALID_ARG
 
