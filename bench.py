@@ -77,18 +77,64 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: str, kclass: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, when it was
-    taken on the current kernel sources and this workload; else None."""
+def read_traffic(workload: str, symbol: str):
+    """HBM bytes per launch of one kernel instantiation from the committed rocprofv3
+    counter summary, when it was taken on the current kernel sources, on this
+    workload and on this very instantiation (tile shape included); else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or not symbol:
         return None
     with open(path) as fh:
         data = json.load(fh)
     if data.get("source_hash") != kernel_source_hash():
         return None
-    ent = data.get("workloads", {}).get(workload, {}).get(kclass)
+    ent = data.get("workloads", {}).get(workload, {}).get(symbol)
     return None if ent is None else ent.get("bytes_per_launch")
+
+
+def copy_ceilings():
+    """Device-copy bandwidth (read + write bytes per second) measured on this GPU with
+    torch events: a 1 GiB copy (HBM-resident) and a repeated 48 MiB copy (96 MiB of
+    source and destination: past the 32 MiB of L2 caches, inside the 256 MiB
+    Infinity Cache, like the 2-D workload's vectors)."""
+    import torch
+    out = {}
+    for name, nbytes, ring, reps in (("hbm", 1 << 30, 1, 4), ("mall", 48 << 20, 1, 64)):
+        n = nbytes // 8
+        src = [torch.ones(n, dtype=torch.float64, device="cuda") for _ in range(ring)]
+        dst = [torch.empty_like(x) for x in src]
+        for k in range(ring):
+            dst[k].copy_(src[k])
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for r in range(reps):
+            dst[r % ring].copy_(src[r % ring])
+        b.record()
+        b.synchronize()
+        out[name + "_copy_gbs"] = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+        del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def host_info():
+    """CPU model, logical cores and RAM of the host."""
+    model, ram = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "host_ram_gib": ram}
 
 
 class Stepper:
@@ -120,6 +166,8 @@ class Stepper:
         self.u = self.us[0]
         self.m = 0
         self.iters = 0
+        self.sweeps = 0
+        self.true_res = -1.0
         self.status = 0
 
     def step(self):
@@ -141,6 +189,8 @@ class Stepper:
         s, st = R.rsfde_step(self.S.h, self.m * self.inst.dt, self.es, self.fs, self.us)
         self.status = max(self.status, s)
         self.iters += sum(x["iters"] for x in st)
+        self.sweeps += sum(x["outer_sweeps"] for x in st)
+        self.true_res = max([self.true_res] + [x["rel_true_res"] for x in st])
         self.m += 1
 
     def close(self):
@@ -175,45 +225,84 @@ def cpu_baseline_batch(insts, nsample: int):
         got = g.us[k].cpu().numpy()
         par = max(par, float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)))
     g.close()
-    return {
+    out = {
         "value": (n_s / n_all) / dt, "unit": "time-steps/s", "cores": int(threads), "kind": "oracle",
         "sample": f"first step of instances 0..{nsample - 1} ({n_s} of {n_all} unknowns) in {dt:.1f} s, "
                   f"scaled to the whole batch by unknown count",
         "parity_rel_diff_gpu_vs_oracle": par,
     }
+    out.update(host_info())
+    return out
 
 
-def cpu_baseline(inst, steps: int):
-    """Time the FP64 oracle on `steps` steps from psi on the host, and the GPU on the
-    same steps for a parity figure."""
-    import numpy as np
-    import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+def _oracle_steps(O, inst, steps, rtol=None):
+    from dataclasses import replace
+    if rtol is not None:
+        inst = replace(inst, rtol=rtol, max_cycles=max(inst.max_cycles, 20))
     P = O.OracleProblem(inst)
     u = P.psi()
-    t0 = time.perf_counter()
     its = []
+    t0 = time.perf_counter()
+    big = inst.size > 4_000_000
+
+    def progress(k, r):
+        # the large grids take seconds per oracle iteration: report each one
+        if big:
+            print(f"oracle step {len(its)}: iteration {k}, residual {r:.2e}, "
+                  f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+
     for m in range(steps):
-        u, st = P.step(u, m)
+        u, st = P.step(u, m, progress=progress)
         its.append(st["iters"])
-    dt = time.perf_counter() - t0
-    g = Stepper(inst)
-    for _ in range(steps):
-        g.step()
-    got = g.u.cpu().numpy()
-    g.close()
-    ref = u.ravel()
-    par = float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
-    return {
+    return u.ravel(), its, time.perf_counter() - t0
+
+
+def cpu_baseline(inst, steps: int, tight: bool = True, one_thread_steps: int = 1):
+    """Time the FP64 oracle on `steps` steps from psi on the host cores, and on
+    `one_thread_steps` steps with one thread; run the GPU's FP64 and mixed forms on the
+    same steps for parity figures: FP64 against the oracle (same Krylov sequence),
+    mixed against the oracle solved to 1e-13 (the mixed form iterates along another
+    sequence, so it is held to the exact solution of each step's system)."""
+    import numpy as np
+    import oracle as O
+    from paper_2404_10221_amd import rsfde as R
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+        threads = os.cpu_count() or 1
+    ref, its, dt = _oracle_steps(O, inst, steps)
+
+    def rel(a, b):
+        return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+    def gpu(**over):
+        g = Stepper(inst, **over)
+        for _ in range(steps):
+            g.step()
+        got = g.u.cpu().numpy()
+        g.close()
+        return got
+
+    out = {
         "value": steps / dt, "unit": "time-steps/s", "cores": int(threads), "kind": "oracle",
         "sample": f"first {steps} of the {inst.M} steps from psi (dense-matrix FP64 oracle, "
                   f"{sum(its)} GMRES iterations); {dt:.1f} s wall",
-        "parity_rel_diff_gpu_vs_oracle": par,
+        "parity_rel_diff_gpu_vs_oracle": rel(gpu(), ref),
     }
+    out.update(host_info())
+    if tight:
+        ref_t, its_t, dt_t = _oracle_steps(O, inst, steps, rtol=1e-13)
+        out["parity_rel_diff_mixed_gpu_vs_oracle_rtol_1e-13"] = rel(gpu(precision=R.RSFDE_MIXED), ref_t)
+        out["rel_diff_oracle_vs_oracle_rtol_1e-13"] = rel(ref, ref_t)
+    if one_thread_steps and threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            _, its1, dt1 = _oracle_steps(O, inst, one_thread_steps)
+        out["one_thread"] = {"value": one_thread_steps / dt1, "unit": "time-steps/s",
+                             "sample": f"first {one_thread_steps} step(s), {sum(its1)} GMRES "
+                                       f"iterations, {dt1:.1f} s wall"}
+    return out
 
 
 def main():
@@ -293,7 +382,8 @@ def main():
     symbol = pass_symbol(R, g.S.h, inst, dom) if len(insts) == 1 else None
     g.close()
     achieved = (by / n) / ((ms / n) * 1e-3) / 1e9 if n else 0.0
-    traffic = read_traffic(args.workload, dom)
+    traffic = read_traffic(args.workload, symbol)
+    ceil = copy_ceilings()
     out = {
         "metric": METRIC,
         "value": K / elapsed,
@@ -316,28 +406,52 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "launches_timed": n, "avg_launch_us": 1e3 * ms / n if n else None,
             "algorithmic_bytes_per_launch": by / n if n else None,
+            "copy_ceilings_gbs": {k: round(v, 1) for k, v in ceil.items()},
+            "frac_of_hbm_copy": achieved / ceil["hbm_copy_gbs"],
+            "frac_of_mall_copy": achieved / ceil["mall_copy_gbs"],
+            "launches": "launches that exited on the status word past the end of their "
+                        "GMRES cycle are left out",
         },
         "kernel_time_share_warmup": {k: round(v[1], 4) for k, v in tot.items()},
     }
 
-    # ---- mixed FP32 operator + FP64 refinement on the same steps
-    if not args.no_mixed:
-        gm = Stepper(insts, precision=R.RSFDE_MIXED)
+    def rel(xs, ys):
+        return max(float((a - b).abs().max() / b.abs().max().clamp_min(1e-300)) for a, b in zip(xs, ys))
+
+    def timed_leg(**over):
+        gl = Stepper(insts, **over)
         for _ in range(W):
-            gm.step()
-        it0 = gm.iters
+            gl.step()
+        it0, sw0 = gl.iters, gl.sweeps
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(K):
-            gm.step()
+            gl.step()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        diff = max(float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
-                   for a, b in zip(gm.us, u64))
-        out["mixed"] = {"value": K / el, "unit": "time-steps/s", "ms_per_step": 1e3 * el / K,
-                        "gmres_iters_per_step": (gm.iters - it0) / K,
-                        "rel_diff_vs_fp64_gpu": diff, "status": gm.status}
-        gm.close()
+        us = [u.clone() for u in gl.us]
+        res = {"value": K / el, "unit": "time-steps/s", "ms_per_step": 1e3 * el / K,
+               "gmres_iters_per_step": (gl.iters - it0) / K,
+               "outer_sweeps_per_step": (gl.sweeps - sw0) / K,
+               "max_rel_true_res": gl.true_res, "status": gl.status}
+        gl.close()
+        return res, us
+
+    # ---- mixed FP32 operator + FP64 refinement on the same steps, at equal accuracy:
+    # every form's distance from a tight solve (FP64 to rtol 1e-14) of the same steps,
+    # and the FP64 form run to the mixed form's own stopping bound (rtol / 10 on the
+    # FP64 preconditioned residual)
+    if not args.no_mixed:
+        _, tight = timed_leg(rtol=1e-14, max_cycles=50)
+        res, um = timed_leg(precision=R.RSFDE_MIXED)
+        res["rel_diff_vs_fp64_gpu"] = rel(um, u64)
+        res["rel_diff_vs_tight_solve"] = rel(um, tight)
+        res["outer_rtol"] = 0.1 * inst.rtol
+        out["mixed"] = res
+        res, ub = timed_leg(rtol=0.1 * inst.rtol)
+        res["rel_diff_vs_tight_solve"] = rel(ub, tight)
+        out["fp64_at_mixed_bound"] = res
+        out["config"]["rel_diff_vs_tight_solve"] = rel(u64, tight)
 
     # ---- two-sided form (eq. Pls, FP64) on the same steps: more passes per iteration
     if not args.no_two_sided:
@@ -396,8 +510,15 @@ def main():
         gg.close()
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = (cpu_baseline(inst, args.cpu_steps) if len(insts) == 1
-                               else cpu_baseline_batch(insts, args.cpu_instances))
+        if len(insts) > 1:
+            out["cpu_baseline"] = cpu_baseline_batch(insts, args.cpu_instances)
+        else:
+            # bounded samples: the 3-D workloads take seconds (255^3) to a minute
+            # (511^3) per oracle step on the host
+            steps = {"C3": 2, "C5": 1}.get(args.workload, args.cpu_steps)
+            small = args.workload in ("C1", "C2")
+            out["cpu_baseline"] = cpu_baseline(inst, steps, tight=small,
+                                               one_thread_steps=1 if small else 0)
     print(json.dumps(out), flush=True)
 
 

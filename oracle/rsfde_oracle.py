@@ -531,7 +531,8 @@ class OracleProblem:
 
     # -- one Crank-Nicolson step
     def step(self, u: np.ndarray, m: int, x0_mode: int = 0, restart: Optional[int] = None,
-             rtol: Optional[float] = None, max_cycles: Optional[int] = None):
+             rtol: Optional[float] = None, max_cycles: Optional[int] = None,
+             progress: Optional[Callable] = None):
         th = self.t_half(m)
         e = self.e_at(th)
         F = self.F_from_closure(self.f_closure_at(th))
@@ -540,7 +541,8 @@ class OracleProblem:
         x, st = gmres_left(lambda v: self.apply_A(e, v), self.apply_prec_inv, b, x0,
                            restart=self.inst.restart if restart is None else restart,
                            rtol=self.inst.rtol if rtol is None else rtol,
-                           max_cycles=self.inst.max_cycles if max_cycles is None else max_cycles)
+                           max_cycles=self.inst.max_cycles if max_cycles is None else max_cycles,
+                           progress=progress)
         return x, st
 
 
@@ -708,11 +710,13 @@ class PointOracle:
 # ----------------------------------------------------------------------------
 
 def gmres_left(apply_A: Callable, apply_Minv: Callable, b: np.ndarray, x0: np.ndarray,
-               restart: int, rtol: float, max_cycles: int = 10):
+               restart: int, rtol: float, max_cycles: int = 10,
+               progress: Optional[Callable] = None):
     """Textbook restarted GMRES on M^{-1} A x = M^{-1} b (Saad-Schultz): modified
     Gram-Schmidt Arnoldi, Givens rotations on the Hessenberg matrix.  Stops at the
     first iteration k with ||M^{-1}(b - A x_k)||_2 <= rtol ||M^{-1}(b - A x_0)||_2, the
-    residual norm being the least-squares value |g_{k+1}|."""
+    residual norm being the least-squares value |g_{k+1}|.  progress(iteration,
+    relative residual), when given, is called after every iteration (reporting only)."""
     x = x0.copy()
     z = apply_Minv(b - apply_A(x))
     beta0 = float(np.linalg.norm(z))
@@ -752,6 +756,8 @@ def gmres_left(apply_A: Callable, apply_Minv: Callable, b: np.ndarray, x0: np.nd
             stats["iters"] += 1
             k = j + 1
             stats["rel_pres"] = abs(g[j + 1]) / beta0
+            if progress is not None:
+                progress(stats["iters"], stats["rel_pres"])
             if abs(g[j + 1]) <= rtol * beta0:
                 done = True
                 break

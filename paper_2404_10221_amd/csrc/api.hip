@@ -197,6 +197,8 @@ struct TimedPass {
   hipEvent_t a, b;
   double bytes;
   int cls;
+  int step;   // Arnoldi step the launch belongs to (-1: not an Arnoldi step)
+  bool spec;  // launched past the end of its cycle: exited on the status word
 };
 
 }  // namespace
@@ -301,6 +303,7 @@ struct rsfde_ctx {
   std::vector<hipEvent_t> ev_free;
   long long t_launches[RSFDE_K_NCLASS] = {0};
   double t_ms[RSFDE_K_NCLASS] = {0}, t_bytes[RSFDE_K_NCLASS] = {0};
+  int cur_step = -1;  // Arnoldi step whose launches are being issued (timing tag)
 };
 
 static hipError_t get_event(rsfde_ctx* h, hipEvent_t* ev) {
@@ -321,7 +324,7 @@ static int timed_launch(rsfde_ctx* h, int cls, double bytes, Fn fn) {
     CK(get_event(h, &ea));
     CK(get_event(h, &eb));
     CK(fn(ea, eb));
-    h->pending.push_back(TimedPass{ea, eb, bytes, cls});
+    h->pending.push_back(TimedPass{ea, eb, bytes, cls, h->cur_step, false});
   } else {
     CK(fn(nullptr, nullptr));
   }
@@ -522,14 +525,24 @@ static int run_pass(rsfde_ctx* h, const Inst& I, const PassArgs& a, bool fp32) {
   });
 }
 
+// Timed launches of Arnoldi steps >= kend ran past the end of their cycle (the
+// host launches chunks of steps speculatively; such kernels exit on the status
+// word): they are left out of the timing.
+static void mark_speculative(rsfde_ctx* h, int kend) {
+  for (auto& tp : h->pending)
+    if (tp.step >= kend) tp.spec = true;
+}
+
 static int flush_timing(rsfde_ctx* h) {
   for (auto& tp : h->pending) {
-    float ms = 0.f;
-    CK(hipEventSynchronize(tp.b));
-    CK(hipEventElapsedTime(&ms, tp.a, tp.b));
-    h->t_ms[tp.cls] += ms;
-    h->t_bytes[tp.cls] += tp.bytes;
-    h->t_launches[tp.cls] += 1;
+    if (!tp.spec) {
+      float ms = 0.f;
+      CK(hipEventSynchronize(tp.b));
+      CK(hipEventElapsedTime(&ms, tp.a, tp.b));
+      h->t_ms[tp.cls] += ms;
+      h->t_bytes[tp.cls] += tp.bytes;
+      h->t_launches[tp.cls] += 1;
+    }
     h->ev_free.push_back(tp.a);
     h->ev_free.push_back(tp.b);
   }
@@ -852,7 +865,10 @@ static int read_summary(rsfde_ctx* h, const Inst& I, GmresSummary* out) {
   CK(hipMemcpyAsync(h->pinned, &I.st->sum, sizeof(GmresSummary), hipMemcpyDeviceToHost, h->stream));
   CK(hipStreamSynchronize(h->stream));
   *out = *h->pinned;
-  if (!h->pending.empty()) CKS(flush_timing(h));
+  if (!h->pending.empty()) {
+    if (out->flag != GM_RUNNING) mark_speculative(h, out->k);
+    CKS(flush_timing(h));
+  }
   return RSFDE_OK;
 }
 
@@ -909,6 +925,7 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
     for (int jj = j; jj < jend; ++jj) {
       const int pend = jj == j ? pending : jj - 1;
       auto launch = [&]() -> int {
+        h->cur_step = jj;
         double* vj = I.V + (int64_t)jj * I.ldv;
         double* w = I.V + (int64_t)(jj + 1) * I.ldv;
         GmRes g;
@@ -937,6 +954,7 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
                          [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(2, ka, h->stream, ea, eb); }));
         CKS(timed_launch(h, RSFDE_K_ORTH_NORM, vb * (jj + 3),
                          [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(3, ka, h->stream, ea, eb); }));
+        h->cur_step = -1;
         return RSFDE_OK;
       };
       if (h->graphs && h->tmask == 0) {
@@ -1331,7 +1349,15 @@ static int read_summaries(rsfde_ctx* h, const KPlan& kp) {
   CK(hipMemcpyAsync(h->psum, h->dsum, kp.ninst * sizeof(GmresSummary), hipMemcpyDeviceToHost,
                     h->stream));
   CK(hipStreamSynchronize(h->stream));
-  if (!h->pending.empty()) CKS(flush_timing(h));
+  if (!h->pending.empty()) {
+    // a batched launch of step j did work while some instance's cycle had not
+    // ended before j (instances that ended earlier exit inside it)
+    int kend = 0;
+    for (int s = 0; s < kp.ninst; ++s)
+      kend = std::max(kend, h->psum[s].flag == GM_RUNNING ? RSFDE_MAX_RESTART + 1 : h->psum[s].k);
+    mark_speculative(h, kend);
+    CKS(flush_timing(h));
+  }
   return RSFDE_OK;
 }
 
@@ -1357,6 +1383,7 @@ static int run_cycle_batched(rsfde_ctx* h, const std::vector<int>& S, bool fp32,
     for (int jj = j; jj < jend; ++jj) {
       const int pend = jj == j ? pending : jj - 1;
       auto launch = [&]() -> int {
+        h->cur_step = jj;
         CKS(launch_chain_batched(h, bp.oper, jj, pend));
         for (int w = 1; w <= 3; ++w) {
           const KLaunch kl = klaunch(bp.kp, false, jj, -1, 0, nullptr);
@@ -1365,6 +1392,7 @@ static int run_cycle_batched(rsfde_ctx* h, const std::vector<int>& S, bool fp32,
             return kry_sweep_batched(w, kl, bp.kp.nb_total, h->stream, ea, eb);
           }));
         }
+        h->cur_step = -1;
         return RSFDE_OK;
       };
       if (h->graphs && h->tmask == 0 && &bp == &h->full) {

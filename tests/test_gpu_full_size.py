@@ -8,6 +8,8 @@ one from the definitions:
 One full time step is then checked through its stopping rule:
 ||(B P)^{-1}(b - A u^{m+1})|| <= rtol ||(B P)^{-1}(b - A u^m)||, with the operators
 just verified."""
+import os
+
 import numpy as np
 import pytest
 
@@ -159,3 +161,60 @@ def test_full_size_fields_and_one_step(name):
     assert err_e <= 1e-13 and err_f <= 1e-11
     assert st == R.RSFDE_OK and stats[0]["converged"] == 1
     assert n1 / n0 <= inst.rtol + slack
+
+
+@pytest.mark.parametrize("name,steps", [
+    ("C3", 2),
+    pytest.param("C5", 1, marks=pytest.mark.skipif(
+        os.environ.get("RSFDE_FULL_C5") != "1",
+        reason="one oracle step of the 511^3 grid takes about 3 minutes of host time; "
+               "set RSFDE_FULL_C5=1 (bench.py --workload C5 records the same parity)")),
+])
+def test_full_size_solution_against_oracle(name, steps):
+    """The first time steps of the full 3-D workloads through rsfde_solve's sampling
+    of the registered fields, against the dense oracle's run on the same grid
+    (same ebar, same Krylov sequence): relative solution difference <= 1e-10."""
+    import time
+    inst = config(name)
+    say(f"[full {name}] {steps} step(s) against the oracle, n = {inst.size}")
+    t0 = time.perf_counter()
+    ref = O.run(inst, steps=steps)
+    t_or = time.perf_counter() - t0
+    S = _solver(inst)
+    R.rsfde_set_ebar(S.h, 0, ref["ebar"], ref["ebar"])
+    u = empty(inst.size)
+    R.rsfde_eval_field(S.h, 0, R.WHICH_PSI, 0.0, u)
+    status, st = R.rsfde_solve(S.h, steps, [u])
+    got = host(u)
+    S.close()
+    d = float(np.max(np.abs(got - ref["u"])) / np.max(np.abs(ref["u"])))
+    say(f"   rel diff {d:.3e}; iters gpu {st[0]['iters']} oracle {sum(ref['iters'])}; "
+        f"oracle {t_or:.1f} s")
+    assert status == R.RSFDE_OK
+    assert st[0]["iters"] == sum(ref["iters"])
+    assert d <= 1e-10
+
+
+def test_full_size_batched_instances_against_oracle():
+    """One step of the first four instances of the 64-instance workload at their real
+    grid sizes, batched on one handle, against the oracle instance by instance."""
+    from dataclasses import replace
+    insts = [replace(i, M=16) for i in config("C4")[:4]]
+    say(f"[full C4] 4 instances {[i.n for i in insts]}, one step")
+    refs = [O.run(i, steps=1) for i in insts]
+    S = R.Solver([R.params_from_instance(i) for i in insts])
+    us = []
+    for k, (inst, ref) in enumerate(zip(insts, refs)):
+        R.rsfde_set_fields(S.h, k, inst.e, inst.f, inst.psi)
+        R.rsfde_set_ebar(S.h, k, ref["ebar"], ref["ebar"])
+        us.append(empty(inst.size))
+        R.rsfde_eval_field(S.h, k, R.WHICH_PSI, 0.0, us[k])
+    status, st = R.rsfde_solve(S.h, 1, us)
+    got = [host(u) for u in us]
+    S.close()
+    assert status == R.RSFDE_OK
+    for k, ref in enumerate(refs):
+        d = float(np.max(np.abs(got[k] - ref["u"])) / np.max(np.abs(ref["u"])))
+        say(f"   inst {k} n={insts[k].n}: rel diff {d:.3e}, iters {st[k]['iters']} / {ref['iters'][0]}")
+        assert st[k]["iters"] == ref["iters"][0]
+        assert d <= 1e-10
