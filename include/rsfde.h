@@ -230,6 +230,21 @@ int rsfde_apply_A(rsfde_handle h, int instance, const double* e, const double* v
  * tau preconditioner (eqs. Pa, tauSalpha, diag); needs ebar to be set. */
 int rsfde_apply_prec(rsfde_handle h, int instance, const double* r, double* out);
 
+/* The same (B_alpha P_alpha)^{-1} r as rsfde_apply_prec, bit for bit, for callers that
+ * cannot allocate device memory or bring a workspace for temporaries (code under
+ * HIP graph capture, tight serving loops).  The pass temporaries (none for d = 1,
+ * two FP64 vectors for d = 2, four for d = 3) live in a static device array of
+ * RSFDE_NOALLOC_SCRATCH_BYTES per GPU, held by the library until the process
+ * ends; the call itself allocates nothing and creates no events (kernel timing is
+ * suspended for it).  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (two streams, two threads) race and must be ordered by the caller.
+ * Nothing in the array needs to start at zero (every pass writes its whole output).
+ * Errors: RSFDE_E_INVALID_ARG, RSFDE_E_STATE (ebar not set), RSFDE_E_WORKSPACE (the
+ * temporaries, each rounded up to 256 bytes, exceed RSFDE_NOALLOC_SCRATCH_BYTES:
+ * more than 2^22 unknowns in 2-D or 2^21 in 3-D), RSFDE_E_HIP. */
+#define RSFDE_NOALLOC_SCRATCH_BYTES (64u << 20)
+int rsfde_apply_prec_noalloc(rsfde_handle h, int instance, const double* r, double* out);
+
 /* out = S diag(g) S r for one of the sine-basis diagonals g of Section 3, with
  * Lambda_K the eigenvalues of B_alpha and mu_K those of B_alpha P_alpha:
  *   RSFDE_PREC_BP_INV     (B_alpha P_alpha)^{-1}       g = 1/mu      (as rsfde_apply_prec)

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -16,6 +17,38 @@
 #include "pass_sizes.h"
 #include "rsfde.h"
 #include "setup.h"
+
+// ---------------------------------------------------------------------------
+// Device scratch of rsfde_apply_prec_noalloc: a file-scope array (one copy per
+// GPU, held until the process ends).  Host code never uses its name as an
+// address: the device address is taken once per device with
+// hipGetSymbolAddress (scratch_ptr) and passed to the kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[RSFDE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+// Device address of `scratch` on the current device (resolved on first use per
+// device; later calls return the stored address).
+static hipError_t scratch_ptr(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // per-length dispatch
@@ -554,9 +587,10 @@ static int flush_timing(rsfde_ctx* h) {
 // a factor of the two-sided form.  Temporaries T[0], T[1], T[2], T[3] in turn
 // (d = 3); out may be T[2], r may be T[3].
 static int run_prec(rsfde_ctx* h, const Inst& I, bool fp32, const double* r, double* out,
-                    int pmode = PM_BP_INV, const int* stop_fl = nullptr) {
+                    int pmode = PM_BP_INV, const int* stop_fl = nullptr,
+                    void* const* temps = nullptr) {
   const int d = I.d;
-  void* const* T = I.tmp;
+  void* const* T = temps ? temps : I.tmp;
   if (d == 1) {
     PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
     t.flags = FL_IN64 | FL_OUT64;
@@ -1712,6 +1746,12 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
   const int v = rsfde_workspace_size(p, count, &need);
   if (v != RSFDE_OK) return v;
   if (!workspace || bytes < need || ((uintptr_t)workspace & 255)) return RSFDE_E_WORKSPACE;
+  {
+    // the no-allocation entry point's device scratch: take its address on this
+    // device now (set-up), so the entry point itself only looks it up
+    void* sp = nullptr;
+    CK(scratch_ptr(&sp));
+  }
   rsfde_ctx* h = new (std::nothrow) rsfde_ctx();
   if (!h) return RSFDE_E_INVALID_ARG;
   h->count = count;
@@ -2137,6 +2177,26 @@ int rsfde_apply_prec(rsfde_handle h, int instance, const double* r, double* out)
   Inst& I = h->inst[instance];
   if (!I.ebar_set) return RSFDE_E_STATE;
   return run_prec(h, I, false, r, out);
+}
+
+int rsfde_apply_prec_noalloc(rsfde_handle h, int instance, const double* r, double* out) {
+  if (!h || instance < 0 || instance >= h->count || !r || !out) return RSFDE_E_INVALID_ARG;
+  Inst& I = h->inst[instance];
+  if (!I.ebar_set) return RSFDE_E_STATE;
+  // temporaries: 2 (d - 1) FP64 vectors, each starting on a 256-byte boundary
+  const int ntemp = I.d == 1 ? 0 : (I.d == 2 ? 2 : 4);
+  const size_t vec = ((size_t)I.n * sizeof(double) + 255) & ~(size_t)255;
+  if ((size_t)ntemp * vec > (size_t)RSFDE_NOALLOC_SCRATCH_BYTES) return RSFDE_E_WORKSPACE;
+  void* base = nullptr;
+  CK(scratch_ptr(&base));
+  void* T[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int k = 0; k < ntemp; ++k) T[k] = (char*)base + (size_t)k * vec;
+  // no event creation either: kernel timing is suspended for this call
+  const unsigned mask = h->tmask;
+  h->tmask = 0;
+  const int st = run_prec(h, I, false, r, out, PM_BP_INV, nullptr, T);
+  h->tmask = mask;
+  return st;
 }
 
 int rsfde_apply_prec_form(rsfde_handle h, int instance, int form, const double* r, double* out) {

@@ -41,6 +41,7 @@ EXPORTED = (
     "rsfde_eval_field_batch", "rsfde_set_graph", "rsfde_apply_A",
     "rsfde_apply_prec", "rsfde_apply_prec_form", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
     "rsfde_get_timing", "rsfde_prescan_ebar", "rsfde_get_pass_shape", "rsfde_set_true_residual",
+    "rsfde_apply_prec_noalloc",
 )
 
 K_CLASSES = ("mv_first", "mv_mid", "mv_last", "dst", "dsd", "dots", "orth_dots", "orth_norm", "update")
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_eval_field_batch.argtypes = [P, I, D, C.POINTER(P)]
     lib.rsfde_apply_A.argtypes = [P, I, P, P, P]
     lib.rsfde_apply_prec.argtypes = [P, I, P, P]
+    lib.rsfde_apply_prec_noalloc.argtypes = [P, I, P, P]
     lib.rsfde_apply_prec_form.argtypes = [P, I, I, P, P]
     lib.rsfde_compute_F.argtypes = [P, I, P, P]
     lib.rsfde_rhs.argtypes = [P, I, P, P, P, P]
@@ -262,6 +264,11 @@ def rsfde_apply_A(h, instance: int, e, v, out) -> None:
 
 def rsfde_apply_prec(h, instance: int, r, out) -> None:
     _check(load_library().rsfde_apply_prec(h, instance, _ptr(r), _ptr(out)), "rsfde_apply_prec")
+
+
+def rsfde_apply_prec_noalloc(h, instance: int, r, out) -> None:
+    _check(load_library().rsfde_apply_prec_noalloc(h, instance, _ptr(r), _ptr(out)),
+           "rsfde_apply_prec_noalloc")
 
 
 def rsfde_apply_prec_form(h, instance: int, form: int, r, out) -> None:
