@@ -305,10 +305,22 @@ int rsfde_set_graph(rsfde_handle h, int enable);
  * (transform = 1), in the FP64 chains (precision = RSFDE_FP64) or the FP32 inner
  * chains of the mixed form (RSFDE_MIXED).  *length = L = 2(N_axis + 1), the
  * transform length; *per_workgroup = complex transforms per workgroup (two real
- * pencils each).  The pass kernel is rsfde_pass_kernel<R, L, per_workgroup,
- * axis > 0>.  Host only.  Errors: RSFDE_E_INVALID_ARG. */
+ * pencils each).  The pass kernel is rsfde_pass_kernel<R, code, per_workgroup,
+ * axis > 0> (rsfde_dst_kernel for transform passes) with the plan code of
+ * rsfde_get_pass_plan.  Host only.  Errors: RSFDE_E_INVALID_ARG. */
 int rsfde_get_pass_shape(rsfde_handle h, int instance, int axis, int precision, int transform,
                          int* length, int* per_workgroup);
+
+/* Radix plan the autotuner picked for the same pencil pass as rsfde_get_pass_shape:
+ * *code is the pass kernel's length template argument (L for the length's default
+ * plan, L + 65536 for its alternative plan) and radices[0 .. *nstage) the radices
+ * of its Stockham stages (radices: room for 8).  The autotuner times both plans
+ * of a length where it has two (2(N+1) >= 256) with three tile widths each, and
+ * keeps its choices per GPU architecture for the process (and, with
+ * RSFDE_TUNE_CACHE=<file>, across processes).  Host only.
+ * Errors: RSFDE_E_INVALID_ARG. */
+int rsfde_get_pass_plan(rsfde_handle h, int instance, int axis, int precision, int transform,
+                        int* code, int* radices, int* nstage);
 
 /* Kernel classes for HIP-event timing (bit i of the mask enables class i). */
 #define RSFDE_K_MV_FIRST    0  /* first-axis operator pass */

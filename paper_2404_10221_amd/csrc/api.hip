@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <string>
 #include <mutex>
 #include <cmath>
 #include <new>
@@ -127,6 +128,17 @@ static void pass_shape_rt(int L, bool fp32, bool strided, int var, int* nt, int*
   }
   *nt = 0;
   *ppt = 0;
+}
+
+static bool pass_plan_rt(int L, int var, int* code, int* radix, int* nstage) {
+  switch (L) {
+#define RSFDE_CASE(LL) \
+  case LL:             \
+    return pass_plan<LL>(var, code, radix, nstage);
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  return false;
 }
 
 static hipError_t launch_dht(int L, const DhtArgs& a, int64_t nblocks, hipStream_t s) {
@@ -322,10 +334,6 @@ struct rsfde_ctx {
   const int* fjob_start = nullptr;
   std::vector<RecPass>* rec = nullptr;  // chain recording instead of launching
   int rec_inst = -1;
-  struct AtEntry {
-    int fp, ax, cls, L, var;
-  };
-  std::vector<AtEntry> atc;  // batched handles: one tile variant per (precision, axis, class, L)
   bool true_res = false;                 // rsfde_set_true_residual
   hipStream_t stream = nullptr;
   GmresSummary* pinned = nullptr;
@@ -1619,22 +1627,103 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
 }
 
 // ---------------------------------------------------------------------------
-// tile autotuner: time the workgroup-shape variants of every pass kind the
-// chains use (operator pass and transform pass, per axis and precision) on the
-// instance's own grid and keep the fastest.  The variants only change how many
-// pencils a workgroup holds; the arithmetic per pencil is the same, so the
-// choice never changes results.  RSFDE_NO_AUTOTUNE=1 keeps variant 0.
+// tile and radix-plan autotuner: time the variants of every pass kind the chains
+// use (operator pass and transform pass, per axis and precision) on the
+// instance's own grid and keep the fastest.  Variants 0 .. 2 change only how many
+// pencils a workgroup holds (bitwise the same results); variants 3 .. 5 run the
+// length's alternative radix plan (the same transform, rounded differently).
+// Choices are kept per device architecture in a process-wide cache keyed by
+// (dimension, axis, precision, pass kind, length), so that every handle of the
+// process -- one instance or many -- runs the same kernels for the same pass and
+// batched and one-at-a-time runs stay bit-identical; RSFDE_TUNE_CACHE=<file>
+// keeps the cache across processes.  RSFDE_NO_AUTOTUNE=1 keeps variant 0;
+// RSFDE_FORCE_VARIANT=v runs variant v wherever the length has it (tests).
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, int>> g_tune;  // key -> variant
+bool g_tune_loaded = false;
+}  // namespace
+
+static std::string tune_key(const char* arch, int d, int ax, int fp, int cls, int L) {
+  char b[160];
+  snprintf(b, sizeof b, "%s d%d ax%d fp%d cls%d L%d", arch, d, ax, fp, cls, L);
+  return b;
+}
+
+// Looks the key up (loading the cache file once); -1 when absent.
+static int tune_lookup(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune_loaded) {
+    g_tune_loaded = true;
+    const char* path = getenv("RSFDE_TUNE_CACHE");
+    if (path && path[0]) {
+      FILE* fh = fopen(path, "r");
+      if (fh) {
+        char line[256];
+        while (fgets(line, sizeof line, fh)) {
+          char* eq = strrchr(line, '=');
+          if (!eq) continue;
+          *eq = 0;
+          const int v = atoi(eq + 1);
+          if (v >= 0 && v < RSFDE_PASS_VARIANTS) g_tune.emplace_back(line, v);
+        }
+        fclose(fh);
+      }
+    }
+  }
+  for (const auto& e : g_tune)
+    if (e.first == key) return e.second;
+  return -1;
+}
+
+static void tune_store(const std::string& key, int v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.emplace_back(key, v);
+  const char* path = getenv("RSFDE_TUNE_CACHE");
+  if (path && path[0]) {
+    FILE* fh = fopen(path, "a");
+    if (fh) {
+      fprintf(fh, "%s=%d\n", key.c_str(), v);
+      fclose(fh);
+    }
+  }
+}
+
 static int autotune(rsfde_ctx* h, Inst& I) {
   const char* off = getenv("RSFDE_NO_AUTOTUNE");
   if (off && off[0] == '1') return RSFDE_OK;
+  const char* fv = getenv("RSFDE_FORCE_VARIANT");
+  const int forced = fv && fv[0] ? atoi(fv) : -1;
   const char* vb = getenv("RSFDE_AUTOTUNE_VERBOSE");
   const bool verbose = vb && vb[0] == '1';
+  const int nprec = I.p.precision == RSFDE_MIXED ? 2 : 1;
+  const int d = I.d;
+  if (forced >= 0) {
+    for (int ax = 0; ax < d; ++ax)
+      for (int fp = 0; fp < nprec; ++fp)
+        for (int cls = 0; cls < 2; ++cls) {
+          int nt = 0, ppt = 0;
+          pass_shape_rt(I.ax[ax].L, fp == 1, ax > 0, forced, &nt, &ppt);
+          I.var[ax][fp][cls] = nt > 0 ? forced : 0;
+        }
+    return RSFDE_OK;
+  }
+  char arch[64] = "gfx";
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      strncpy(arch, prop.gcnArchName, sizeof arch - 1);
+      arch[sizeof arch - 1] = 0;
+      for (char* c = arch; *c; ++c)
+        if (*c == ' ' || *c == '=') *c = '_';
+    }
+  }
   for (int k = 0; k < 4; ++k) CK(fill_f64((double*)I.tmp[k], I.n, 0.0, h->stream));
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  const int nprec = I.p.precision == RSFDE_MIXED ? 2 : 1;
-  const int d = I.d;
   int status = RSFDE_OK;
   for (int ax = 0; ax < d && status == RSFDE_OK; ++ax) {
     for (int fp = 0; fp < nprec && status == RSFDE_OK; ++fp) {
@@ -1655,25 +1744,31 @@ static int autotune(rsfde_ctx* h, Inst& I) {
           op = OP_MV_LAST;
           flags = FL_DST_AFTER;
         }
-        // variants interleaved over three rounds, each timing two launches whose
-        // inputs and outputs rotate over the four temporaries (inputs are not
-        // left cache-resident by the previous launch); the best round counts
         const int L = I.ax[ax].L;
-        if (h->count > 1) {
-          // instances of one handle share a variant per (precision, axis, class, L),
-          // so that batched launches group them
-          int cached = -1;
-          for (const auto& e : h->atc)
-            if (e.fp == fp && e.ax == ax && e.cls == cls && e.L == L) cached = e.var;
-          if (cached >= 0) {
+        const std::string key = tune_key(arch, d, ax, fp, cls, L);
+        const int cached = tune_lookup(key);
+        if (cached >= 0) {
+          int nt = 0, ppt = 0;
+          pass_shape_rt(L, fp == 1, ax > 0, cached, &nt, &ppt);
+          if (nt > 0) {
             I.var[ax][fp][cls] = cached;
             continue;
           }
         }
+        // variants interleaved over three rounds, each timing two launches whose
+        // inputs and outputs rotate over the four temporaries (inputs are not
+        // left cache-resident by the previous launch); the best round counts
         float tbest[RSFDE_PASS_VARIANTS];
-        for (int v = 0; v < RSFDE_PASS_VARIANTS; ++v) tbest[v] = 1e30f;
+        bool have[RSFDE_PASS_VARIANTS];
+        for (int v = 0; v < RSFDE_PASS_VARIANTS; ++v) {
+          int nt = 0, ppt = 0;
+          pass_shape_rt(L, fp == 1, ax > 0, v, &nt, &ppt);
+          have[v] = nt > 0;
+          tbest[v] = 1e30f;
+        }
         for (int rep = 0; rep < 3 && status == RSFDE_OK; ++rep) {
           for (int v = 0; v < RSFDE_PASS_VARIANTS && status == RSFDE_OK; ++v) {
+            if (!have[v]) continue;
             I.var[ax][fp][cls] = v;
             PassArgs t = mk_pass(I, ax, op, fp == 1);
             t.flags = flags;
@@ -1698,15 +1793,19 @@ static int autotune(rsfde_ctx* h, Inst& I) {
             if (ms < tbest[v]) tbest[v] = ms;
           }
         }
+        // the default plan's widest tile unless another variant is 3 % faster
         int bestv = 0;
         for (int v = 1; v < RSFDE_PASS_VARIANTS; ++v)
-          if (tbest[v] < tbest[bestv] * 0.97f) bestv = v;
-        if (verbose)
-          fprintf(stderr, "rsfde autotune: axis %d %s %s pass: %.1f %.1f %.1f us per launch -> variant %d\n",
-                  ax, fp ? "fp32" : "fp64", cls ? "transform" : "operator", 500.f * tbest[0],
-                  500.f * tbest[1], 500.f * tbest[2], bestv);
+          if (have[v] && tbest[v] < tbest[bestv] * 0.97f) bestv = v;
+        if (verbose) {
+          fprintf(stderr, "rsfde autotune: %s axis %d %s %s pass, L %d:", arch, ax,
+                  fp ? "fp32" : "fp64", cls ? "transform" : "operator", L);
+          for (int v = 0; v < RSFDE_PASS_VARIANTS; ++v)
+            if (have[v]) fprintf(stderr, " v%d %.1f", v, 500.f * tbest[v]);
+          fprintf(stderr, " us per launch -> variant %d\n", bestv);
+        }
         I.var[ax][fp][cls] = bestv;
-        if (h->count > 1) h->atc.push_back(rsfde_ctx::AtEntry{fp, ax, cls, L, bestv});
+        if (status == RSFDE_OK) tune_store(key, bestv);
       }
     }
   }
@@ -2255,6 +2354,20 @@ int rsfde_get_pass_shape(rsfde_handle h, int instance, int axis, int precision, 
   pass_shape_rt(L, fp32, axis > 0, I.var[axis][fp32 ? 1 : 0][transform], &nt, &ppt);
   *length = L;
   *per_workgroup = ppt / 2;
+  return RSFDE_OK;
+}
+
+int rsfde_get_pass_plan(rsfde_handle h, int instance, int axis, int precision, int transform,
+                        int* code, int* radices, int* nstage) {
+  if (!h || instance < 0 || instance >= h->count || !code || !radices || !nstage)
+    return RSFDE_E_INVALID_ARG;
+  const Inst& I = h->inst[instance];
+  if (axis < 0 || axis >= I.d || (transform != 0 && transform != 1)) return RSFDE_E_INVALID_ARG;
+  if (precision != RSFDE_FP64 && precision != RSFDE_MIXED) return RSFDE_E_INVALID_ARG;
+  const bool fp32 = precision == RSFDE_MIXED;
+  if (fp32 && I.p.precision != RSFDE_MIXED) return RSFDE_E_INVALID_ARG;
+  if (!pass_plan_rt(I.ax[axis].L, I.var[axis][fp32 ? 1 : 0][transform], code, radices, nstage))
+    return RSFDE_E_INVALID_ARG;
   return RSFDE_OK;
 }
 

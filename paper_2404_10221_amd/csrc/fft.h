@@ -17,14 +17,24 @@
 
 #include "common.h"
 
-template <int L> struct FftPlan;
+// Templates below are keyed by a plan code: the transform length L (its default
+// radix plan) or L | RSFDE_PLAN_ALT (an alternative plan of the same length, for
+// the lengths that carry one).  The tile autotuner times both.
+#define RSFDE_PLAN_ALT (1 << 16)
+constexpr int plan_len(int code) { return code & (RSFDE_PLAN_ALT - 1); }
+
+template <int LC> struct FftPlan;
+template <int L> struct HasAltPlan { static constexpr bool value = false; };
 
 #define RSFDE_PLAN(L_, E_, ...)                                                  \
   template <> struct FftPlan<L_> {                                               \
-    static constexpr int Lv = L_, E = E_, T = L_ / E_;                           \
+    static constexpr int Lv = plan_len(L_), E = E_, T = plan_len(L_) / E_;        \
     static constexpr int R[] = {__VA_ARGS__};                                    \
     static constexpr int NS = sizeof(R) / sizeof(int);                           \
   };
+#define RSFDE_ALT_PLAN(L_, E_, ...)                                              \
+  RSFDE_PLAN(L_ | RSFDE_PLAN_ALT, E_, __VA_ARGS__)                               \
+  template <> struct HasAltPlan<L_> { static constexpr bool value = true; };
 
 RSFDE_PLAN(8, 8, 8)
 RSFDE_PLAN(12, 12, 4, 3)
@@ -45,6 +55,18 @@ RSFDE_PLAN(1536, 24, 8, 8, 8, 3)
 RSFDE_PLAN(2048, 8, 8, 8, 8, 4)
 RSFDE_PLAN(3072, 24, 8, 8, 8, 3, 2)
 RSFDE_PLAN(4096, 16, 16, 16, 16)
+// alternatives: the other side of the trade between threads per transform (more
+// wavefronts in flight) and radix (fewer LDS round trips)
+RSFDE_ALT_PLAN(256, 8, 8, 8, 4)
+RSFDE_ALT_PLAN(384, 24, 8, 8, 3, 2)
+RSFDE_ALT_PLAN(512, 16, 16, 16, 2)
+RSFDE_ALT_PLAN(768, 24, 8, 8, 4, 3)
+RSFDE_ALT_PLAN(1024, 16, 16, 16, 4)
+RSFDE_ALT_PLAN(1536, 12, 4, 4, 4, 4, 3, 2)
+RSFDE_ALT_PLAN(2048, 16, 16, 16, 8)
+RSFDE_ALT_PLAN(3072, 12, 4, 4, 4, 4, 4, 3)
+RSFDE_ALT_PLAN(4096, 8, 8, 8, 8, 8)
+#undef RSFDE_ALT_PLAN
 #undef RSFDE_PLAN
 
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
@@ -59,7 +81,7 @@ constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 template <typename R, int L>
 struct LdsSeq {
   static constexpr int BS = 256 / (int)sizeof(cpx<R>);  // elements per 256-byte row
-  static constexpr int size = L + L / BS;                // slots of one sequence
+  static constexpr int size = plan_len(L) + plan_len(L) / BS;  // slots of one sequence
   cpx<R>* p;
   __device__ __forceinline__ static constexpr int pos(int i) { return i + i / BS; }
   __device__ __forceinline__ cpx<R>& operator[](int i) const { return p[pos(i)]; }
@@ -79,7 +101,7 @@ template <int L> struct StageNs<L, 0> { static constexpr int value = 1; };
 // the registers to the butterflies and the batched global loads.
 template <typename R, int L>
 struct TwHalf {
-  static constexpr int H = L / 2;
+  static constexpr int H = plan_len(L) / 2;
   static constexpr int BS = 256 / (int)sizeof(cpx<R>);
   static constexpr int size = H + H / BS;
   const cpx<R>* tab;
@@ -291,7 +313,7 @@ template <typename R, int L, int S>
 struct StageGeom {
   using P = FftPlan<L>;
   static constexpr int RAD = P::R[S], Ns = StageNs<L, S>::value;
-  static constexpr int T = P::T, E = P::E, NB = E / RAD, LR = L / RAD;
+  static constexpr int T = P::T, E = P::E, NB = E / RAD, LR = P::Lv / RAD;
   static_assert(E % RAD == 0, "radix must divide the per-thread element count");
   // slot of element t + T m in the stage's register layout
   static constexpr int slot(int m) { return (m % NB) * RAD + m / NB; }
@@ -327,7 +349,7 @@ __device__ __forceinline__ void stage_math(int t, const TW& tw, cpx<R>* v) {
     const int j = t + b * G::T;
     if constexpr (Ns > 1) {
       const int k = j % Ns;
-      constexpr int step = L / (Ns * RAD);
+      constexpr int step = plan_len(L) / (Ns * RAD);
       cpx<R> w[RAD];
       tw_powers<R, RAD, DIR, S>(tw, k * step, w);
 #pragma unroll

@@ -98,9 +98,8 @@ __device__ __forceinline__ void set_comp(cpx<R>& z, int c, R v) {
 }
 
 // Pencils packed per workgroup: F complex transforms, i.e. 2F real pencils.
-// Variant VAR halves F VAR times; the host picks a variant per axis by timing
-// them at setup (the tile autotuner).
-#define RSFDE_PASS_VARIANTS 3
+// Tile variant VAR halves F VAR times; the host picks a variant (tile width and
+// radix plan) per axis by timing them at setup (the tile autotuner).
 
 // Pitch (in elements) of the F sequences of a workgroup.  In a strided tile the
 // lanes of a wavefront cover 2F pencils at consecutive positions, i.e. the same
@@ -123,7 +122,7 @@ struct PassShape {
   // LDS left for the transforms: 160 KB minus the twiddle table, the circulant spectrum
   // and 2 KB for the small shared arrays (block sums, Givens column, y)
   static constexpr int cap =
-      160 * 1024 - TwHalf<R, L>::size * (int)sizeof(cpx<R>) - L * (int)sizeof(R) - 2048;
+      160 * 1024 - TwHalf<R, L>::size * (int)sizeof(cpx<R>) - plan_len(L) * (int)sizeof(R) - 2048;
   static constexpr int want = 512 / T > 1 ? 512 / T : 1;
   static constexpr int lim = cap / bytes_per_fft;
   static constexpr int F0a = want < lim ? want : lim;
@@ -150,7 +149,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   __shared__ cpx<R> twl[TwHalf<R, L>::size];
   // circulant spectrum / L (operator passes), or the axis-0 tables of OP_DSD;
   // not used by the strided sine-transform kernel
-  __shared__ R chs[STRIDED && MODE == PK_TR ? 1 : L];
+  __shared__ R chs[STRIDED && MODE == PK_TR ? 1 : plan_len(L)];
 
   const int tid = threadIdx.x;
   const TwHalf<R, L> tw{twl};
@@ -273,7 +272,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   // passes, or the axis-0 eigenvalue tables lambda (first N entries) and
   // eta q / lambda (next N) of the transform-scale-transform pass, plus that
   // pass's per-pencil factors from the other (already transformed) axes.
-  constexpr int CH = (L + NT - 1) / NT;
+  constexpr int Lv = plan_len(L);  // transform length (L is the plan code)
+  constexpr int CH = (Lv + NT - 1) / NT;
   // (the 1/mu scaling runs along the contiguous axis only)
   const bool is_dsd = !STRIDED && !mv_op && a.op == OP_DSD;
   R lt[CH];
@@ -285,7 +285,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
     const R* __restrict__ cg = (const R*)a.chat;
     static_for<CH>([&](auto q) {
       const int k = tid + q.value * NT;
-      lt[q.value] = cg[k < L ? k : 0];
+      lt[q.value] = cg[k < Lv ? k : 0];
     });
   } else if (is_dsd) {
     const R* __restrict__ l0 = (const R*)a.lam[0];
@@ -335,7 +335,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   if (mv_op || is_dsd) {
     static_for<CH>([&](auto q) {
       const int k = tid + q.value * NT;
-      if (L % NT == 0 || k < L) chs[k] = lt[q.value];
+      if (Lv % NT == 0 || k < Lv) chs[k] = lt[q.value];
     });
   }
 
@@ -809,85 +809,148 @@ template <typename R, int L>
 hipError_t launch_pass_batched_L(const BLaunch& bl, int64_t nblocks, bool strided, int var,
                                  hipStream_t s, hipEvent_t ea, hipEvent_t eb);
 
-// Workgroup shape of a variant (threads, pencils per tile).
+// Variants of a length: 0 .. 2 run the default radix plan with F, F/2, F/4
+// transforms per workgroup, 3 .. 5 the alternative plan (where the length has
+// one) with the same three tile widths.
+#define RSFDE_PASS_VARIANTS 6
+
+// Workgroup shape of a variant (threads, pencils per tile); 0 threads for a
+// variant the length does not have.
 template <typename R, int L>
 inline void pass_shape(bool strided, int var, int* nt, int* pencils_per_tile) {
-#define RSFDE_SHAPE_CASE(V)                                        \
-  if (var == V) {                                                  \
+#define RSFDE_SHAPE_CASE(LC, V, VI)                                \
+  if (var == VI) {                                                 \
     if (strided) {                                                 \
-      *nt = PassShape<R, L, true, V>::NT;                          \
-      *pencils_per_tile = 2 * PassShape<R, L, true, V>::F;         \
+      *nt = PassShape<R, LC, true, V>::NT;                         \
+      *pencils_per_tile = 2 * PassShape<R, LC, true, V>::F;        \
     } else {                                                       \
-      *nt = PassShape<R, L, false, V>::NT;                         \
-      *pencils_per_tile = 2 * PassShape<R, L, false, V>::F;        \
+      *nt = PassShape<R, LC, false, V>::NT;                        \
+      *pencils_per_tile = 2 * PassShape<R, LC, false, V>::F;       \
     }                                                              \
     return;                                                        \
   }
-  RSFDE_SHAPE_CASE(0)
-  RSFDE_SHAPE_CASE(1)
-  RSFDE_SHAPE_CASE(2)
+  RSFDE_SHAPE_CASE(L, 0, 0)
+  RSFDE_SHAPE_CASE(L, 1, 1)
+  RSFDE_SHAPE_CASE(L, 2, 2)
+  if constexpr (HasAltPlan<L>::value) {
+    RSFDE_SHAPE_CASE((L | RSFDE_PLAN_ALT), 0, 3)
+    RSFDE_SHAPE_CASE((L | RSFDE_PLAN_ALT), 1, 4)
+    RSFDE_SHAPE_CASE((L | RSFDE_PLAN_ALT), 2, 5)
+  }
 #undef RSFDE_SHAPE_CASE
   *nt = 0;
   *pencils_per_tile = 0;
 }
 
-// One launch of kernel K<R, L, F, STRIDED> in the tile shape of variant V.
-#define RSFDE_LAUNCH_ONE(K, R, L, V, STR)                                                       \
+// Radices of the plan a variant runs (radix[0..*nstage)); false for a variant the
+// length does not have.
+template <int L>
+inline bool pass_plan(int var, int* code, int* radix, int* nstage) {
+  auto fill = [&](auto plan, int c) {
+    using P = decltype(plan);
+    *code = c;
+    *nstage = P::NS;
+    for (int k = 0; k < P::NS; ++k) radix[k] = P::R[k];
+  };
+  if (var >= 0 && var < 3) {
+    fill(FftPlan<L>{}, L);
+    return true;
+  }
+  if constexpr (HasAltPlan<L>::value) {
+    if (var >= 3 && var < 6) {
+      fill(FftPlan<L | RSFDE_PLAN_ALT>{}, L | RSFDE_PLAN_ALT);
+      return true;
+    }
+  }
+  return false;
+}
+
+// One launch of kernel K<R, LC, F, STRIDED> in the tile shape of tile variant V.
+#define RSFDE_LAUNCH_ONE(K, R, LC, V, STR)                                                      \
   {                                                                                             \
-    using S = PassShape<R, L, STR, V>;                                                          \
-    if (ea) hipExtLaunchKernelGGL((K<R, L, S::F, STR>), dim3((unsigned)a.nlaunch), dim3(S::NT), \
+    using S = PassShape<R, LC, STR, V>;                                                         \
+    if (ea) hipExtLaunchKernelGGL((K<R, LC, S::F, STR>), dim3((unsigned)a.nlaunch), dim3(S::NT),\
                                   0, s, ea, eb, 0, a);                                          \
-    else hipLaunchKernelGGL((K<R, L, S::F, STR>), dim3((unsigned)a.nlaunch), dim3(S::NT), 0, s, \
+    else hipLaunchKernelGGL((K<R, LC, S::F, STR>), dim3((unsigned)a.nlaunch), dim3(S::NT), 0, s,\
                             a);                                                                 \
   }
 
-#define RSFDE_LAUNCH_VARIANT(R, L, V)                                                           \
-  if (var == V) {                                                                               \
+#define RSFDE_LAUNCH_VARIANT(R, LC, V, VI)                                                      \
+  if (var == VI) {                                                                              \
     const bool mv = a.op <= OP_MV_LAST;                                                         \
     if (strided) {                                                                              \
-      if (mv) RSFDE_LAUNCH_ONE(rsfde_pass_kernel, R, L, V, true)                                \
-      else RSFDE_LAUNCH_ONE(rsfde_dst_kernel, R, L, V, true)                                    \
+      if (mv) RSFDE_LAUNCH_ONE(rsfde_pass_kernel, R, LC, V, true)                               \
+      else RSFDE_LAUNCH_ONE(rsfde_dst_kernel, R, LC, V, true)                                   \
     } else {                                                                                    \
-      if (mv) RSFDE_LAUNCH_ONE(rsfde_pass_kernel, R, L, V, false)                               \
-      else RSFDE_LAUNCH_ONE(rsfde_dst_kernel, R, L, V, false)                                   \
+      if (mv) RSFDE_LAUNCH_ONE(rsfde_pass_kernel, R, LC, V, false)                              \
+      else RSFDE_LAUNCH_ONE(rsfde_dst_kernel, R, LC, V, false)                                  \
     }                                                                                           \
     return hipGetLastError();                                                                   \
   }
 
-#define RSFDE_LAUNCH_BATCHED_ONE(R, L, V, STR, MODE)                                           \
+#define RSFDE_LAUNCH_BATCHED_ONE(R, LC, V, STR, MODE)                                          \
   {                                                                                             \
-    using S = PassShape<R, L, STR, V>;                                                          \
-    hipExtLaunchKernelGGL((rsfde_pass_batched<R, L, S::F, STR, MODE>), dim3((unsigned)nblocks), \
+    using S = PassShape<R, LC, STR, V>;                                                         \
+    hipExtLaunchKernelGGL((rsfde_pass_batched<R, LC, S::F, STR, MODE>), dim3((unsigned)nblocks),\
                           dim3(S::NT), 0, s, ea, eb, 0, bl);                                    \
   }
 
-#define RSFDE_LAUNCH_BATCHED_VARIANT(R, L, V)                                                   \
-  if (var == V) {                                                                               \
+#define RSFDE_LAUNCH_BATCHED_VARIANT(R, LC, V, VI)                                              \
+  if (var == VI) {                                                                              \
     if (strided) {                                                                              \
-      if (bl.mv) RSFDE_LAUNCH_BATCHED_ONE(R, L, V, true, PK_MV)                                 \
-      else RSFDE_LAUNCH_BATCHED_ONE(R, L, V, true, PK_TR)                                       \
+      if (bl.mv) RSFDE_LAUNCH_BATCHED_ONE(R, LC, V, true, PK_MV)                                \
+      else RSFDE_LAUNCH_BATCHED_ONE(R, LC, V, true, PK_TR)                                      \
     } else {                                                                                    \
-      if (bl.mv) RSFDE_LAUNCH_BATCHED_ONE(R, L, V, false, PK_MV)                                \
-      else RSFDE_LAUNCH_BATCHED_ONE(R, L, V, false, PK_TR)                                      \
+      if (bl.mv) RSFDE_LAUNCH_BATCHED_ONE(R, LC, V, false, PK_MV)                               \
+      else RSFDE_LAUNCH_BATCHED_ONE(R, LC, V, false, PK_TR)                                     \
     }                                                                                           \
     return hipGetLastError();                                                                   \
   }
+
+// Variants 0 .. 2 of plan code LC (returns hipErrorInvalidValue for others).
+template <typename R, int LC>
+inline hipError_t launch_pass_plan(const PassArgs& a, bool strided, int var, hipStream_t s,
+                                   hipEvent_t ea, hipEvent_t eb) {
+  RSFDE_LAUNCH_VARIANT(R, LC, 0, 0)
+  RSFDE_LAUNCH_VARIANT(R, LC, 1, 1)
+  RSFDE_LAUNCH_VARIANT(R, LC, 2, 2)
+  return hipErrorInvalidValue;
+}
+template <typename R, int LC>
+inline hipError_t launch_pass_batched_plan(const BLaunch& bl, int64_t nblocks, bool strided,
+                                           int var, hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
+  RSFDE_LAUNCH_BATCHED_VARIANT(R, LC, 0, 0)
+  RSFDE_LAUNCH_BATCHED_VARIANT(R, LC, 1, 1)
+  RSFDE_LAUNCH_BATCHED_VARIANT(R, LC, 2, 2)
+  return hipErrorInvalidValue;
+}
+// All six variants of length L (the alternative plan only where L has one).
+template <typename R, int L>
+inline hipError_t launch_pass_all(const PassArgs& a, bool strided, int var, hipStream_t s,
+                                  hipEvent_t ea, hipEvent_t eb) {
+  if (var < 3) return launch_pass_plan<R, L>(a, strided, var, s, ea, eb);
+  if constexpr (HasAltPlan<L>::value)
+    return launch_pass_plan<R, L | RSFDE_PLAN_ALT>(a, strided, var - 3, s, ea, eb);
+  return hipErrorInvalidValue;
+}
+template <typename R, int L>
+inline hipError_t launch_pass_batched_all(const BLaunch& bl, int64_t nblocks, bool strided,
+                                          int var, hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
+  if (var < 3) return launch_pass_batched_plan<R, L>(bl, nblocks, strided, var, s, ea, eb);
+  if constexpr (HasAltPlan<L>::value)
+    return launch_pass_batched_plan<R, L | RSFDE_PLAN_ALT>(bl, nblocks, strided, var - 3, s, ea, eb);
+  return hipErrorInvalidValue;
+}
 
 #define RSFDE_INSTANTIATE_PASS(R, L)                                                         \
   template <>                                                                                \
   hipError_t launch_pass_L<R, L>(const PassArgs& a, bool strided, int var, hipStream_t s,   \
                                  hipEvent_t ea, hipEvent_t eb) {                           \
-    RSFDE_LAUNCH_VARIANT(R, L, 0)                                                            \
-    RSFDE_LAUNCH_VARIANT(R, L, 1)                                                            \
-    RSFDE_LAUNCH_VARIANT(R, L, 2)                                                            \
-    return hipErrorInvalidValue;                                                             \
+    return launch_pass_all<R, L>(a, strided, var, s, ea, eb);                                \
   }                                                                                          \
   template <>                                                                                \
   hipError_t launch_pass_batched_L<R, L>(const BLaunch& bl, int64_t nblocks, bool strided,  \
                                          int var, hipStream_t s, hipEvent_t ea,             \
                                          hipEvent_t eb) {                                   \
-    RSFDE_LAUNCH_BATCHED_VARIANT(R, L, 0)                                                    \
-    RSFDE_LAUNCH_BATCHED_VARIANT(R, L, 1)                                                    \
-    RSFDE_LAUNCH_BATCHED_VARIANT(R, L, 2)                                                    \
-    return hipErrorInvalidValue;                                                             \
+    return launch_pass_batched_all<R, L>(bl, nblocks, strided, var, s, ea, eb);              \
   }

@@ -41,7 +41,7 @@ EXPORTED = (
     "rsfde_eval_field_batch", "rsfde_set_graph", "rsfde_apply_A",
     "rsfde_apply_prec", "rsfde_apply_prec_form", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
     "rsfde_get_timing", "rsfde_prescan_ebar", "rsfde_get_pass_shape", "rsfde_set_true_residual",
-    "rsfde_apply_prec_noalloc",
+    "rsfde_apply_prec_noalloc", "rsfde_get_pass_plan",
 )
 
 K_CLASSES = ("mv_first", "mv_mid", "mv_last", "dst", "dsd", "dots", "orth_dots", "orth_norm", "update")
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_get_timing.argtypes = [P, I, C.POINTER(C.c_longlong), C.POINTER(D), C.POINTER(D)]
     lib.rsfde_prescan_ebar.argtypes = [P, I, I]
     lib.rsfde_get_pass_shape.argtypes = [P, I, I, I, I, C.POINTER(I), C.POINTER(I)]
+    lib.rsfde_get_pass_plan.argtypes = [P, I, I, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(I)]
     for name in EXPORTED:
         getattr(lib, name)
         if name != "rsfde_strerror":
@@ -301,6 +302,15 @@ def rsfde_get_pass_shape(h, instance: int, axis: int, precision: int, transform:
     _check(load_library().rsfde_get_pass_shape(h, instance, axis, precision, transform,
                                                C.byref(L), C.byref(F)), "rsfde_get_pass_shape")
     return L.value, F.value
+
+
+def rsfde_get_pass_plan(h, instance: int, axis: int, precision: int, transform: int):
+    """(plan code, radices) of the radix plan the autotuner picked for a pencil pass."""
+    code, n = C.c_int(0), C.c_int(0)
+    rad = (C.c_int * 8)()
+    _check(load_library().rsfde_get_pass_plan(h, instance, axis, precision, transform, C.byref(code),
+                                              rad, C.byref(n)), "rsfde_get_pass_plan")
+    return int(code.value), [int(rad[k]) for k in range(n.value)]
 
 
 def rsfde_set_graph(h, enable: bool) -> None:
