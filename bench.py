@@ -54,16 +54,18 @@ WORKLOAD_TEXT = {
 
 
 def pass_symbol(R, h, inst, kclass: str):
-    """Kernel instantiation the tile autotuner picked for a pencil-pass class (the
-    name rocprofv3 reports), or None for the other classes."""
+    """Kernel instantiation the autotuner picked for a pencil-pass class (the name
+    rocprofv3 reports: the length argument is the plan code, L or L + 65536), or
+    None for the other classes."""
     d = inst.d
     where = {"mv_first": (0, 0), "mv_mid": (1, 0), "mv_last": (d - 1, 0), "dsd": (0, 1),
              "dst": (d - 1, 1)}.get(kclass)
     if where is None or where[0] >= d:
         return None
     L, F = R.rsfde_get_pass_shape(h, 0, where[0], R.RSFDE_FP64, where[1])
+    code, _ = R.rsfde_get_pass_plan(h, 0, where[0], R.RSFDE_FP64, where[1])
     kern = "rsfde_dst_kernel" if where[1] else "rsfde_pass_kernel"
-    return f"{kern}<double, {L}, {F}, {'true' if where[0] > 0 else 'false'}>"
+    return f"{kern}<double, {code}, {F}, {'true' if where[0] > 0 else 'false'}>"
 
 
 def kernel_source_hash() -> str:
