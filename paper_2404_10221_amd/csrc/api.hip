@@ -724,10 +724,13 @@ static int run_strang_prec(rsfde_ctx* h, const Inst& I, const double* r, int ri,
   return RSFDE_OK;
 }
 
-enum Chain { CH_APPLY_A = 0, CH_RHS = 1, CH_RESID = 2, CH_OPER = 3 };
+enum Chain { CH_APPLY_A = 0, CH_RHS = 1, CH_RESID = 2, CH_OPER = 3, CH_R0 = 4 };
 
 // Operator chains along the axes (x_1 first).  CH_APPLY_A: out = A x.
 // CH_RHS: out = B E x - S x + xcoef * xin.  CH_RESID: out = M (xin - A x).
+// CH_R0: out = M (xcoef * xin - 2 S x), the step's first residual
+// M (b - A u^{(m)}) with b = (B E - S) u^{(m)} + dt F written out (the B E terms
+// cancel), one-sided form only.
 // CH_OPER: out = M A (sc * x).  M = (BP)^{-1} in the one-sided form; in the
 // two-sided form (eq. Pls) M = P^{-1/2} B^{-1} and CH_OPER first takes x to
 // P^{-1/2} x (into T[2]; the step's scale is applied when the next pass reads
@@ -740,7 +743,7 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
   const bool strang = I.p.method == RSFDE_SPGM && (kind == CH_RESID || kind == CH_OPER);
   // the tau preconditioner fused into the operator passes (not in the Strang form,
   // whose solve follows the operator as its own chain from a temporary)
-  const bool prec = (kind == CH_RESID || kind == CH_OPER) && !strang;
+  const bool prec = (kind == CH_RESID || kind == CH_OPER || kind == CH_R0) && !strang;
   const int st_i = d == 3 ? 0 : 3;  // Strang form: temporary between the two chains
   double* const op_out = strang ? (double*)I.tmp[st_i] : out;
   const bool two = I.p.method == RSFDE_TPGM;
@@ -752,16 +755,18 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
     x = (const double*)I.tmp[2];
   }
   const double sgn = kind == CH_RHS ? -1.0 : 1.0;
+  const double gam = kind == CH_RESID ? -1.0 : (kind == CH_R0 ? -2.0 : 1.0);
+  const int no_e = kind == CH_R0 ? FL_NO_E : 0;
   void* const* T = I.tmp;
   if (d == 1) {
     PassArgs a = mk_pass(I, 0, OP_MV_LAST, fp32);
-    a.flags = FL_FIRST_IS_LAST | FL_IN64 | FL_OUT64 | (prec ? FL_PREC_FULL : 0);
+    a.flags = FL_FIRST_IS_LAST | FL_IN64 | FL_OUT64 | (prec ? FL_PREC_FULL : 0) | no_e;
     a.pmode = pm;
     a.in_c = x;
     a.sc_ptr = sc;
     a.in_a = e;
     a.eta = sgn * I.ax[0].eta;
-    a.gam = kind == CH_RESID ? -1.0 : 1.0;
+    a.gam = gam;
     a.in_x = xin;
     a.xcoef = xcoef;
     a.out_a = op_out;
@@ -776,7 +781,7 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
   }
   // first axis
   PassArgs a = mk_pass(I, 0, OP_MV_FIRST, fp32);
-  a.flags = FL_IN64;
+  a.flags = FL_IN64 | no_e;
   a.in_c = x;
   a.sc_ptr = sc;
   a.in_a = e;
@@ -806,7 +811,7 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
   z.in_a = T[ia];
   z.in_c = T[ic];
   z.eta = sgn * I.ax[d - 1].eta;
-  z.gam = kind == CH_RESID ? -1.0 : 1.0;
+  z.gam = gam;
   z.in_x = xin;
   z.xcoef = xcoef;
   z.stop_fl = stop_fl;
@@ -1067,8 +1072,29 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
   double al[3] = {I.p.alpha[0], I.p.alpha[1], I.p.alpha[2]};
   CK(compute_F(f_half, gi, al, I.F, h->stream));
   if (mixed) CK(convert_f64_f32(I.ecur, I.e32, I.n, h->stream));
-  // b = (B E - S) u + dt F
-  CKS(run_chain(h, I, CH_RHS, false, u, nullptr, I.F, p.dt, I.b));
+  // One-sided FP64 steps from u^(m) (d >= 2) start from M (dt F - 2 S u^(m)), which
+  // is M (b - A u^(m)) without forming b; b itself is formed from the copy of u^(m)
+  // kept in its buffer only when a restart or the true-residual check needs it.
+  // Handles of several instances keep forming b first, as their batched launches
+  // do, so that batched and one-at-a-time steps of a handle agree bit for bit.
+  const bool r0_path =
+      !mixed && p.x0_mode == 0 && p.method == RSFDE_OPGM && I.d >= 2 && h->count == 1;
+  bool have_b = !r0_path;
+  auto need_b = [&]() -> int {
+    if (!have_b) {
+      // b = (B E - S) u^(m) + dt F from the copy in I.b, written over it (the chain's
+      // first pass reads I.b before its last pass writes it)
+      CKS(run_chain(h, I, CH_RHS, false, I.b, nullptr, I.F, p.dt, I.b));
+      have_b = true;
+    }
+    return RSFDE_OK;
+  };
+  if (r0_path) {
+    CK(hipMemcpyAsync(I.b, u, (size_t)I.n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    // b = (B E - S) u + dt F
+    CKS(run_chain(h, I, CH_RHS, false, u, nullptr, I.F, p.dt, I.b));
+  }
   if (p.x0_mode == 1) CK(fill_f64(u, I.n, 0.0, h->stream));
   rsfde_stats st;
   memset(&st, 0, sizeof(st));
@@ -1082,7 +1108,12 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
   double true_res = -1.0;
   for (int cyc = 0; cyc < max_loops; ++cyc) {
     // z = (BP)^{-1} (b - A u) in FP64 into V_0
-    CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
+    if (cyc == 0 && r0_path) {
+      CKS(run_chain(h, I, CH_R0, false, u, nullptr, I.F, p.dt, I.V));
+    } else {
+      CKS(need_b());
+      CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
+    }
     CK(kry_cycle_init(I.V, I.n, I.st, I.partial, cyc == 0 ? 1 : 0, stop_rtol, inner_rtol,
                       mixed ? 1 : 0, p.restart, h->stream));
     if (mixed && cyc == max_outer) {
@@ -1116,6 +1147,7 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
     true_res = S.beta0 > 0 ? S.beta / S.beta0 : 0.0;
   } else if (h->true_res) {
     // recompute z = M (b - A u) in FP64 from the returned u (V_0 is free here)
+    CKS(need_b());
     CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
     CK(kry_cycle_init(I.V, I.n, I.st, I.partial, 0, p.rtol, inner_rtol, 0, p.restart, h->stream));
     GmresSummary R;

@@ -33,7 +33,8 @@ enum : int {
   FL_PREC_FULL = 2,      // MV_LAST (d = 1): follow by transform, 1/mu scaling, transform
   FL_IN64 = 4,           // in_c holds FP64 values (else the pass precision)
   FL_OUT64 = 8,          // out_a receives FP64 values (else the pass precision)
-  FL_FIRST_IS_LAST = 16  // MV_LAST of a one-axis problem: stencil input is e .* v
+  FL_FIRST_IS_LAST = 16, // MV_LAST of a one-axis problem: stencil input is e .* v
+  FL_NO_E = 32           // first operator pass: the B (e .* v) term is dropped (S v alone)
 };
 
 struct PassArgs {
@@ -413,6 +414,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
 
   if (is_mv) {
     const bool ev_mode = op == OP_MV_FIRST || (a.flags & FL_FIRST_IS_LAST);
+    const bool no_e = (a.flags & FL_NO_E) != 0;
     // ---- load (contiguous axis): Toeplitz input c into slots [0,N), stencil
     // input into [N+1, 2N+1); entry N stays zero (the Toeplitz input's padding)
     if (t == 0) {
@@ -430,8 +432,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           R a0 = v0 ? la[2 * i] : (R)0;
           R a1 = v1 ? la[2 * i + 1] : (R)0;
           if (ev_mode) {
-            a0 *= c0;
-            a1 *= c1;
+            a0 = no_e ? (R)0 : a0 * c0;
+            a1 = no_e ? (R)0 : a1 * c1;
           }
           buf[p] = cpx<R>{c0, c1};
           buf[N + 1 + p] = cpx<R>{a0, a1};
@@ -447,7 +449,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           const bool v = pp < nvalid;
           R c = v ? lc[i] * sc : (R)0;
           R av = v ? la[i] : (R)0;
-          if (ev_mode) av *= c;
+          if (ev_mode) av = no_e ? (R)0 : av * c;
           LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
           set_comp(bb[p], pp & 1, c);
           set_comp(bb[N + 1 + p], pp & 1, av);
@@ -473,7 +475,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
       }
       if (ev_mode) {
 #pragma unroll
-        for (int k = 0; k < NE + 2; ++k) ar[k] *= cr[k];
+        for (int k = 0; k < NE + 2; ++k) ar[k] = no_e ? (R)0 : ar[k] * cr[k];
       }
       const LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
 #pragma unroll
