@@ -33,9 +33,9 @@ KCLASS_KERNELS = {
     "mv_last": "rsfde_pass_kernel, last-axis operator pass (B stencil, Toeplitz product, sine transform)",
     "dst": "rsfde_dst_kernel, sine-transform pass",
     "dsd": "rsfde_dst_kernel, sine transform + 1/mu scaling + sine transform",
-    "dots": "k_sweep1 (CGS2 sweep 1)",
-    "orth_dots": "k_sweep2 (CGS2 sweep 2)",
-    "orth_norm": "k_sweep3 (CGS2 sweep 3)",
+    "dots": "k_sweep1 (Arnoldi sweep A: basis dot products)",
+    "orth_dots": "k_sweepB (Arnoldi sweep B: delayed second projection, first projection)",
+    "orth_norm": "(unused)",
     "update": "k_update (Givens resolve + solution update)",
 }
 WORKLOAD_TEXT = {

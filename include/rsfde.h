@@ -328,9 +328,10 @@ int rsfde_get_pass_plan(rsfde_handle h, int instance, int axis, int precision, i
 #define RSFDE_K_MV_LAST     2  /* last-axis operator pass (+ fused sine transform) */
 #define RSFDE_K_DST         3  /* sine-transform pass */
 #define RSFDE_K_DSD         4  /* transform, 1/mu scaling, transform pass */
-#define RSFDE_K_DOTS        5  /* CGS2 sweep 1 */
-#define RSFDE_K_ORTH_DOTS   6  /* CGS2 sweep 2 */
-#define RSFDE_K_ORTH_NORM   7  /* CGS2 sweep 3 + Givens */
+#define RSFDE_K_DOTS        5  /* Arnoldi sweep A: dot products of the basis with w */
+#define RSFDE_K_ORTH_DOTS   6  /* Arnoldi sweep B: second projection of the newest basis
+                                  vector, first projection of w, their dot products */
+#define RSFDE_K_ORTH_NORM   7  /* (no longer launched: CGS2 runs in two sweeps) */
 #define RSFDE_K_UPDATE      8  /* solution update */
 #define RSFDE_K_NCLASS      9
 

@@ -997,10 +997,9 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
         const double vb = 8.0 * (double)I.n;
         CKS(timed_launch(h, RSFDE_K_DOTS, vb * (jj + 2),
                          [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(1, ka, h->stream, ea, eb); }));
-        CKS(timed_launch(h, RSFDE_K_ORTH_DOTS, vb * (jj + 2),
+        // sweep B reads columns 0..j and w, writes column j (j >= 1) and w
+        CKS(timed_launch(h, RSFDE_K_ORTH_DOTS, vb * (jj + 2 + (jj >= 1 ? 2 : 1)),
                          [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(2, ka, h->stream, ea, eb); }));
-        CKS(timed_launch(h, RSFDE_K_ORTH_NORM, vb * (jj + 3),
-                         [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(3, ka, h->stream, ea, eb); }));
         h->cur_step = -1;
         return RSFDE_OK;
       };
@@ -1459,10 +1458,11 @@ static int run_cycle_batched(rsfde_ctx* h, const std::vector<int>& S, bool fp32,
       auto launch = [&]() -> int {
         h->cur_step = jj;
         CKS(launch_chain_batched(h, bp.oper, jj, pend));
-        for (int w = 1; w <= 3; ++w) {
+        for (int w = 1; w <= 2; ++w) {
           const KLaunch kl = klaunch(bp.kp, false, jj, -1, 0, nullptr);
-          const int cls = w == 1 ? RSFDE_K_DOTS : (w == 2 ? RSFDE_K_ORTH_DOTS : RSFDE_K_ORTH_NORM);
-          CKS(timed_launch(h, cls, bp.kp.vbytes * (jj + 2 + (w == 3 ? 1 : 0)), [&](hipEvent_t ea, hipEvent_t eb) {
+          const int cls = w == 1 ? RSFDE_K_DOTS : RSFDE_K_ORTH_DOTS;
+          const int words = w == 1 ? jj + 2 : jj + 2 + (jj >= 1 ? 2 : 1);
+          CKS(timed_launch(h, cls, bp.kp.vbytes * words, [&](hipEvent_t ea, hipEvent_t eb) {
             return kry_sweep_batched(w, kl, bp.kp.nb_total, h->stream, ea, eb);
           }));
         }

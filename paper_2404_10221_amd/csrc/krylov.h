@@ -7,10 +7,14 @@
 // vsc[k] (column k of V is vsc[k] * Vbar_k), so no sweep is spent on scaling.
 //
 // Kernel structure of one Arnoldi step j (no single-block "finish" kernels):
-//   operator passes   w = (BP)^{-1} A v_j   (the first pass resolves step j-1)
-//   sweep 1           partials of Vbar^T w
-//   sweep 2           prologue: h = reduce(sweep-1 partials); w -= V h; partials of Vbar^T w
-//   sweep 3           prologue: h2 = reduce(sweep-2 partials); w -= V h2; partials of ||w||^2
+//   operator passes   w = (BP)^{-1} A qt_j  (the first pass resolves step j-1), where
+//                     column j holds u_j, projected once against the final columns
+//   sweep A           partials of Vbar^T w and Vbar^T u_j
+//   sweep B           prologue: reduce sweep A's partials; per row: q_j = second
+//                     projection of u_j (written over column j), u_{j+1} = first
+//                     projection of w (written over w); partials of ||u_{j+1}||^2
+// (CGS2 with the second projection of each basis vector delayed by one step;
+// see krylov.hip).
 // Step j's Hessenberg column, Givens rotation and stopping test ("resolve j")
 // run in the prologue of the next kernel that needs them: the first operator
 // pass of step j+1, or the solution-update kernel that closes a launched
@@ -71,7 +75,7 @@ inline int kry_blocks(int64_t n) {
 // by the update kernel.
 struct GmRes {
   GmresState* st;
-  const double* p3;  // sweep-3 partials of step `pend`
+  const double* p3;  // sweep-B partials of ||u_{j+1}||^2 of step `pend`
   int nb3;           // number of those partials
   int j;             // step this kernel belongs to
   int pend;          // step to resolve here, or -1

@@ -20,8 +20,8 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
   }
 }
 
-// threads per block for a sweep handling up to KM basis vectors
-// (sweep 2 keeps up to 16 basis values per element in registers for its dots)
+// threads per block for a sweep handling up to KM values (sweep A: sums; sweep B:
+// basis columns with their coefficients)
 template <int W, int KM> struct SweepNT {
   static constexpr int value = W == 2 ? (KM <= 8 ? 1024 : (KM <= 16 ? 512 : 256))
                                       : (KM <= 16 ? 1024 : (KM <= 32 ? 512 : 256));
@@ -218,51 +218,37 @@ __global__ void __launch_bounds__((SweepNT<1, KM>::value)) k_sweep1(const KryArg
   sweep1_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
-// w -= sum_{k < nv} cf[k] V_k at row i (columns in chunks); with KEEP the loaded
-// entries stay in vk for the dot products that follow.
-template <int KM, bool KEEP, typename T>
-__device__ __forceinline__ void sub_cols(T& wi, T (&vk)[KEEP ? KM : 1], const T* __restrict__ V,
-                                         int64_t ld, int64_t i, const double* cf, int nv) {
-  constexpr int CH = KM < 8 ? KM : 8;
-#pragma unroll
-  for (int kb = 0; kb < KM; kb += CH)
-    if (kb < nv) {
-      T v[CH];
-      ld_cols<CH>(v, V, ld, i, kb, nv);
-#pragma unroll
-      for (int c = 0; c < CH; ++c)
-        if (kb + c < nv) {
-          if constexpr (sizeof(T) == 16) {
-            wi.x -= cf[kb + c] * v[c].x;
-            wi.y -= cf[kb + c] * v[c].y;
-          } else {
-            wi -= cf[kb + c] * v[c];
-          }
-          if constexpr (KEEP) vk[kb + c] = v[c];
-        }
-    }
-}
+// ---- Arnoldi step j: CGS2 with the second projection delayed by one step ---------------
+//
+// On entry column j holds u_j, the once-orthogonalised candidate for q_j (scale
+// vsc[j] = 1/||u_j||, so qt = vsc[j] Vbar_j has unit norm) and column j+1 holds
+// w = K qt (the operator of step j applied to qt).  With Q = [q_0 .. q_{j-1}] final:
+//   sweep A   partials of Vbar_k . w and Vbar_k . Vbar_j (k <= j), one pass
+//   sweep B   s = Q^T qt, t = Q^T w, tau = qt . w, r = sqrt(|qt|^2 - |s|^2),
+//             q_j = (qt - Q s) / r                 (second projection of column j)
+//             u_{j+1} = (I - P_{j+1}) w / r = (w - Q (t - c s) - c qt) / r,
+//             c = (tau - s.t) / r^2,
+//             q_j written over column j, u_{j+1} over w, partials of |u_{j+1}|^2.
+// Projecting w and projecting K q_j = (w - K Q s)/r leave the same vector because
+// K Q s lies in the span of Q and q_j (Arnoldi relation).  The Hessenberg column j
+// is t/r (entries < j) and c (entry j); the terms K Q s / r dropped from it are of
+// the size of s, the loss of orthogonality after one projection, as are the
+// second-projection coefficients of plain CGS2.  Two sweeps per Arnoldi step
+// instead of three, and 2j + 6 vector reads and writes instead of 3j + 7.
+// Sweep A holds 2(j+1) sums; past 64 (j >= 32) the sums Vbar_k . Vbar_j come from
+// a third sweep (sweep 1 on column j) into the second partial buffer.
 
-// ---- CGS2 sweep 2: h = Vbar^T w / |v| ; partials of Vbar^T (w - V h) ----------------------
-// (w - V h is formed per row for the dot products and not stored: sweep 3 takes
-// w - V (h + h2) from the unmodified w)
+// Sweep A: partials of Vbar_k . w (values 0..j) and, for j >= 1, Vbar_k . Vbar_j
+// (values j+1 .. 2j+1).
 template <int KM>
-__device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk) {
-  constexpr int NT = SweepNT<2, KM>::value;
+__device__ __forceinline__ void sweepA_body(const KryArgs& a, int bid, int nblk) {
+  constexpr int NT = SweepNT<1, KM>::value;
   constexpr int CH = KM < 8 ? KM : 8;
-  constexpr bool KEEP = KM <= 16;  // basis values kept in registers for the dots
-  GmresState* st = a.st;
-  if (st->FL[a.j] != GM_RUNNING) return;
-  const int nv = a.j + 1;
-  __shared__ double cf[KM];
-  reduce_partials<KM, NT>(a.pa, nblk, nv, cf);
-  if ((int)threadIdx.x < nv) {
-    const double sc = st->vsc[threadIdx.x];
-    const double h = cf[threadIdx.x] * sc;
-    if (bid == 0) st->h[threadIdx.x] = h;
-    cf[threadIdx.x] = h * sc;
-  }
-  __syncthreads();
+  if (a.st->FL[a.j] != GM_RUNNING) return;
+  const int j = a.j;
+  const int nv = j + 1;
+  const bool dual = j >= 1 && 2 * nv <= KM;  // (else the column sums come from sweep D)
+  const int nvals = dual ? 2 * nv : nv;
   double acc[KM];
 #pragma unroll
   for (int k = 0; k < KM; ++k) acc[k] = 0.0;
@@ -273,86 +259,151 @@ __device__ __forceinline__ void sweep2_body(const KryArgs& a, int bid, int nblk)
   const double2* __restrict__ w2 = (const double2*)w;
   const double2* __restrict__ V2 = (const double2*)V;
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
-    double2 wi = w2[i];
-    double2 vk[KEEP ? KM : 1];
-    sub_cols<KM, KEEP>(wi, vk, V2, ld2, i, cf, nv);
+    const double2 wi = w2[i];
+    const double2 uj = V2[(int64_t)j * ld2 + i];
 #pragma unroll
     for (int kb = 0; kb < KM; kb += CH)
       if (kb < nv) {
         double2 v[CH];
-        if constexpr (KEEP) {
+        ld_cols<CH>(v, V2, ld2, i, kb, nv);
 #pragma unroll
-          for (int c = 0; c < CH; ++c) v[c] = vk[kb + c];
-        } else {
-          ld_cols<CH>(v, V2, ld2, i, kb, nv);
+        for (int c = 0; c < CH; ++c) {
+          const int k = kb + c;
+          if (k < nv && k < KM) acc[k] += v[c].x * wi.x + v[c].y * wi.y;
+          if (dual && k < nv && KM / 2 + k < KM && k < KM / 2)
+            acc[KM / 2 + k] += v[c].x * uj.x + v[c].y * uj.y;
         }
-#pragma unroll
-        for (int c = 0; c < CH; ++c)
-          if (kb + c < nv) acc[kb + c] += v[c].x * wi.x + v[c].y * wi.y;
       }
   }
   if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
-    double wi = w[i];
-    double vk[1];
-    sub_cols<KM, false>(wi, vk, V, a.ldv, i, cf, nv);
+    const double wi = w[i], uj = V[(int64_t)j * a.ldv + i];
 #pragma unroll
-    for (int kb = 0; kb < KM; kb += CH)
-      if (kb < nv) {
-        double v[CH];
-        ld_cols<CH>(v, V, a.ldv, i, kb, nv);
-#pragma unroll
-        for (int c = 0; c < CH; ++c)
-          if (kb + c < nv) acc[kb + c] += v[c] * wi;
+    for (int k = 0; k < KM; ++k) {
+      if (k < nv) {
+        const double v = V[(int64_t)k * a.ldv + i];
+        acc[k] += v * wi;
+        if (dual && k < KM / 2) acc[KM / 2 + k] += v * uj;
       }
+    }
   }
+  // values 0..j and KM/2 .. KM/2 + j hold the sums; compact them to 0..j, j+1..2j+1
   __shared__ double res[KM];
-  block_sums<KM, NT>(acc, nv, res);
-  if ((int)threadIdx.x < nv) a.pb[threadIdx.x * RSFDE_PVS + bid] = res[threadIdx.x];
+  block_sums<KM, NT>(acc, KM, res);
+  if ((int)threadIdx.x < nvals) {
+    const int src = (int)threadIdx.x < nv ? (int)threadIdx.x : KM / 2 + ((int)threadIdx.x - nv);
+    a.pa[threadIdx.x * RSFDE_PVS + bid] = res[src];
+  }
 }
 
 template <int KM>
-__global__ void __launch_bounds__((SweepNT<2, KM>::value)) k_sweep2(const KryArgs a) {
-  sweep2_body<KM>(a, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__((SweepNT<1, KM>::value)) k_sweepA(const KryArgs a) {
+  sweepA_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
-// ---- CGS2 sweep 3: h2 = Vbar^T (w - V h) / |v| ; w -= V (h + h2) ; partials of ||w||^2 ---
+// Sweep 1 on column j: partials of Vbar_k . Vbar_j (k <= j) into pb (steps j >= 32).
 template <int KM>
-__device__ __forceinline__ void sweep3_body(const KryArgs& a, int bid, int nblk) {
-  constexpr int NT = SweepNT<3, KM>::value;
+__global__ void __launch_bounds__((SweepNT<1, KM>::value)) k_sweepD(const KryArgs a) {
+  KryArgs d = a;
+  d.w = const_cast<double*>(a.V) + (int64_t)a.j * a.ldv;
+  d.pa = a.pb;
+  sweep1_body<KM>(d, blockIdx.x, gridDim.x);
+}
+
+// Sweep B.  `split`: the sums Vbar_k . Vbar_j are in pb (values 0..j) instead of pa
+// (values j+1 .. 2j+1).
+template <int KM>
+__device__ __forceinline__ void sweepB_body(const KryArgs& a, int bid, int nblk) {
+  constexpr int NT = SweepNT<2, KM>::value;
+  constexpr int CH = KM < 8 ? KM : 8;
   GmresState* st = a.st;
   if (st->FL[a.j] != GM_RUNNING) return;
-  const int nv = a.j + 1;
-  __shared__ double cf[KM];
-  reduce_partials<KM, NT>(a.pb, nblk, nv, cf);
-  if ((int)threadIdx.x < nv) {
-    const double sc = st->vsc[threadIdx.x];
-    const double h2 = cf[threadIdx.x] * sc;
-    if (bid == 0) st->h2[threadIdx.x] = h2;
-    cf[threadIdx.x] = (st->h[threadIdx.x] + h2) * sc;  // both projections from the original w
+  const int j = a.j;
+  const int nv = j + 1;  // columns 0 .. j are read
+  const bool split = 2 * nv > 64;
+  __shared__ double tb[KM], db[KM];
+  __shared__ double cfq[KM], cfu[KM];
+  __shared__ double invr_s;
+  reduce_partials<KM, NT>(a.pa, nblk, nv, tb);
+  if (j >= 1)
+    reduce_partials<KM, NT>(split ? a.pb : a.pa + (int64_t)nv * RSFDE_PVS, nblk, nv, db);
+  if (threadIdx.x < 64) {
+    const int k = threadIdx.x;
+    const double vj = st->vsc[j];
+    const double vk = k <= j ? st->vsc[k] : 0.0;
+    const double sk = k < j ? vk * vj * db[k] : 0.0;
+    const double tk = k <= j ? vk * tb[k] : 0.0;
+    double ss = sk * sk, stt = k < j ? sk * tk : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      ss += __shfl_xor(ss, off, 64);
+      stt += __shfl_xor(stt, off, 64);
+    }
+    const double sig = j >= 1 ? vj * vj * db[j] : 1.0;
+    const double r = sqrt(fmax(sig - gm_lane(ss, 0), 1e-300));
+    const double ir = 1.0 / r;
+    const double tau = gm_lane(tk, j < 64 ? j : 0);
+    const double c = (tau - gm_lane(stt, 0)) * ir * ir;
+    if (k < j) {
+      cfq[k] = sk * vk / vj * ir;
+      cfu[k] = (tk - c * sk) * vk * ir;
+    } else if (k == j) {
+      cfu[k] = c * vj * ir;
+    }
+    if (bid == 0 && k <= j) {
+      st->h[k] = k < j ? tk * ir : c;
+      st->h2[k] = 0.0;
+    }
+    if (k == 0) invr_s = ir;
   }
   __syncthreads();
+  const double ir = invr_s;
   double acc[1] = {0.0};
   double* __restrict__ w = a.w;
-  const double* __restrict__ V = a.V;
+  double* __restrict__ V = const_cast<double*>(a.V);
   const int64_t stride = (int64_t)nblk * NT;
   const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
   double2* __restrict__ w2 = (double2*)w;
-  const double2* __restrict__ V2 = (const double2*)V;
+  double2* __restrict__ V2 = (double2*)V;
   for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
-    double2 wi = w2[i];
-    double2 vk[1];
-    sub_cols<KM, false>(wi, vk, V2, ld2, i, cf, nv);
-    w2[i] = wi;
-    acc[0] += wi.x * wi.x + wi.y * wi.y;
+    const double2 wi = w2[i];
+    double2 qn = {0.0, 0.0}, u = {wi.x * ir, wi.y * ir};
+#pragma unroll
+    for (int kb = 0; kb < KM; kb += CH)
+      if (kb < nv) {
+        double2 v[CH];
+        ld_cols<CH>(v, (const double2*)V2, ld2, i, kb, nv);
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          const int k = kb + cc;
+          if (k < nv) {
+            const double fu = cfu[k];
+            u.x -= fu * v[cc].x;
+            u.y -= fu * v[cc].y;
+            const double fq = k < j ? -cfq[k] : ir;
+            if (k <= j) {
+              qn.x += fq * v[cc].x;
+              qn.y += fq * v[cc].y;
+            }
+          }
+        }
+      }
+    if (j >= 1) V2[(int64_t)j * ld2 + i] = qn;
+    w2[i] = u;
+    acc[0] += u.x * u.x + u.y * u.y;
   }
   if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
-    double wi = w[i];
-    double vk[1];
-    sub_cols<KM, false>(wi, vk, V, a.ldv, i, cf, nv);
-    w[i] = wi;
-    acc[0] += wi * wi;
+    const double wi = w[i];
+    double qn = 0.0, u = wi * ir;
+    for (int k = 0; k < nv; ++k) {
+      const double v = V[(int64_t)k * a.ldv + i];
+      u -= cfu[k] * v;
+      qn += (k < j ? -cfq[k] : ir) * v;
+    }
+    if (j >= 1) V[(int64_t)j * a.ldv + i] = qn;
+    w[i] = u;
+    acc[0] += u * u;
   }
   __shared__ double res[1];
   block_sums<1, NT>(acc, 1, res);
@@ -360,8 +411,8 @@ __device__ __forceinline__ void sweep3_body(const KryArgs& a, int bid, int nblk)
 }
 
 template <int KM>
-__global__ void __launch_bounds__((SweepNT<3, KM>::value)) k_sweep3(const KryArgs a) {
-  sweep3_body<KM>(a, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__((SweepNT<2, KM>::value)) k_sweepB(const KryArgs a) {
+  sweepB_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
 // ---- resolve the last launched step; x += V y when the cycle has finished ----------------
@@ -468,9 +519,21 @@ hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial
 hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
   const int nv = a.j + 1;
   const dim3 g(kry_blocks(a.n));
-  if (which == 1) KRY_SWEEP(k_sweep1, 1, nv, g, a, s);
-  else if (which == 2) KRY_SWEEP(k_sweep2, 2, nv, g, a, s);
-  else KRY_SWEEP(k_sweep3, 3, nv, g, a, s);
+  if (which == 1) {
+    if (a.j >= 1 && 2 * nv <= 64) {
+      KRY_SWEEP(k_sweepA, 1, 2 * nv, g, a, s);
+    } else {
+      KRY_SWEEP(k_sweepA, 1, nv, g, a, s);  // (j = 0, or the sums over columns split off:)
+      if (a.j >= 1) {
+        hipEvent_t ea = nullptr, eb = nullptr;
+        KRY_SWEEP(k_sweepD, 1, nv, g, a, s);
+      }
+    }
+  } else if (which == 2) {
+    KRY_SWEEP(k_sweepB, 2, nv, g, a, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -495,9 +558,16 @@ __global__ void __launch_bounds__((SweepNT<W, KM>::value)) k_sweep_b(const KLaun
   const KBatch& d = kl.desc[slot];
   const KryArgs a = kb_args(d, kl.j);
   const int bid = (int)blockIdx.x - kl.start[slot];
-  if constexpr (W == 1) sweep1_body<KM>(a, bid, d.nb);
-  else if constexpr (W == 2) sweep2_body<KM>(a, bid, d.nb);
-  else sweep3_body<KM>(a, bid, d.nb);
+  if constexpr (W == 1) {
+    sweepA_body<KM>(a, bid, d.nb);
+  } else if constexpr (W == 3) {
+    KryArgs dd = a;  // sums of the columns with column j, into pb (j >= 32)
+    dd.w = const_cast<double*>(a.V) + (int64_t)a.j * a.ldv;
+    dd.pa = a.pb;
+    sweep1_body<KM>(dd, bid, d.nb);
+  } else {
+    sweepB_body<KM>(a, bid, d.nb);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_update_b(const KLaunch kl) {
@@ -537,9 +607,21 @@ hipError_t kry_sweep_batched(int which, const KLaunch& kl, int64_t nblocks, hipS
                              hipEvent_t ea, hipEvent_t eb) {
   const int nv = kl.j + 1;
   const dim3 g((unsigned)nblocks);
-  if (which == 1) KRY_SWEEP_B(1, nv, g, kl, s);
-  else if (which == 2) KRY_SWEEP_B(2, nv, g, kl, s);
-  else KRY_SWEEP_B(3, nv, g, kl, s);
+  if (which == 1) {
+    if (kl.j >= 1 && 2 * nv <= 64) {
+      KRY_SWEEP_B(1, 2 * nv, g, kl, s);
+    } else {
+      KRY_SWEEP_B(1, nv, g, kl, s);
+      if (kl.j >= 1) {
+        hipEvent_t ea = nullptr, eb = nullptr;
+        KRY_SWEEP_B(3, nv, g, kl, s);
+      }
+    }
+  } else if (which == 2) {
+    KRY_SWEEP_B(2, nv, g, kl, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
