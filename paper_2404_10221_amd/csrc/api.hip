@@ -4,6 +4,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <string>
 #include <mutex>
@@ -1667,8 +1669,9 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
 // Choices are kept per device architecture in a process-wide cache keyed by
 // (dimension, axis, precision, pass kind, length), so that every handle of the
 // process -- one instance or many -- runs the same kernels for the same pass and
-// batched and one-at-a-time runs stay bit-identical; RSFDE_TUNE_CACHE=<file>
-// keeps the cache across processes.  RSFDE_NO_AUTOTUNE=1 keeps variant 0;
+// batched and one-at-a-time runs stay bit-identical.  The cache starts from
+// tune_cache.txt beside the library (read only), or from RSFDE_TUNE_CACHE=<file>,
+// which also receives the new choices (one key=variant line each).  RSFDE_NO_AUTOTUNE=1 keeps variant 0;
 // RSFDE_FORCE_VARIANT=v runs variant v wherever the length has it (tests).
 // ---------------------------------------------------------------------------
 namespace {
@@ -1683,14 +1686,27 @@ static std::string tune_key(const char* arch, int d, int ax, int fp, int cls, in
   return b;
 }
 
+// Cache file read when RSFDE_TUNE_CACHE is not set: tune_cache.txt beside the
+// library (the choices shipped with it; read only).
+static std::string default_tune_cache() {
+  Dl_info info;
+  if (dladdr((void*)&default_tune_cache, &info) && info.dli_fname) {
+    std::string p = info.dli_fname;
+    const size_t slash = p.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : p.substr(0, slash)) + "/tune_cache.txt";
+  }
+  return std::string();
+}
+
 // Looks the key up (loading the cache file once); -1 when absent.
 static int tune_lookup(const std::string& key) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (!g_tune_loaded) {
     g_tune_loaded = true;
-    const char* path = getenv("RSFDE_TUNE_CACHE");
-    if (path && path[0]) {
-      FILE* fh = fopen(path, "r");
+    const char* env = getenv("RSFDE_TUNE_CACHE");
+    const std::string path = env && env[0] ? std::string(env) : default_tune_cache();
+    if (!path.empty()) {
+      FILE* fh = fopen(path.c_str(), "r");
       if (fh) {
         char line[256];
         while (fgets(line, sizeof line, fh)) {
