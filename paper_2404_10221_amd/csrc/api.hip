@@ -921,11 +921,25 @@ static int read_summary(rsfde_ctx* h, const Inst& I, GmresSummary* out) {
   return RSFDE_OK;
 }
 
+// Steps still to launch after a chunk that ended at step j_done with the cycle
+// running: the least-squares residual has fallen from beta (cycle start) to res
+// in j_done steps; at the same geometric rate it reaches thr after
+// log(thr/res)/log(rate) more.  One step when the rate says nothing (stagnation).
+static int next_chunk(const GmresSummary& S, int j_done, int left) {
+  if (left <= 1 || j_done <= 0 || !(S.beta > 0.0) || !(S.res > 0.0) || !(S.thr > 0.0)) return 1;
+  const double rate = pow(S.res / S.beta, 1.0 / j_done);
+  if (!(rate > 0.0 && rate < 0.95)) return 1;
+  const double need = ceil(log(S.thr / S.res) / log(rate));
+  if (!(need >= 1.0)) return 1;
+  return need >= (double)left ? left : (int)need;
+}
+
 // Runs one GMRES cycle's iterations after cycle_init, launched in chunks
 // without host synchronisation inside a chunk: the chunk length is the previous
-// cycle's iteration count, then one step at a time.  Kernels of steps past
-// convergence exit on the device status (FL); the update kernel that closes a
-// chunk resolves its last step and adds V y once the cycle has finished.
+// cycle's iteration count, then the steps the residual's rate of decrease
+// predicts (next_chunk).  Kernels of steps past convergence exit on the device
+// status (FL); the update kernel that closes a chunk resolves its last step and
+// adds V y once the cycle has finished.
 // Replay of one Arnoldi step from a graph captured on the private stream: the
 // step's launches have fixed arguments for a given (j, pending resolve), so
 // they are captured once and replayed on the handle's stream.  Used when graph
@@ -1041,7 +1055,7 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
     }
     j = jend;
     pending = -1;
-    chunk = 1;
+    chunk = next_chunk(*S, j, m - j);
     if (j >= m) return RSFDE_OK;  // cannot happen: the last step of a cycle is never running
   }
 }
@@ -1486,13 +1500,14 @@ static int run_cycle_batched(rsfde_ctx* h, const std::vector<int>& S, bool fp32,
       return kry_update_batched(ku, bp.kp.nbu_total, h->stream, ea, eb);
     }));
     CKS(read_summaries(h, bp.kp));
-    int running = 0;
+    int running = 0, need = 1;
     bool newly = false;
     for (int s = 0; s < ns; ++s) {
       if (done[s]) continue;
       const GmresSummary& G = h->psum[s];
       if (G.flag == GM_RUNNING) {
         ++running;
+        need = std::max(need, next_chunk(G, jend, bp.kp.m - jend));
       } else {
         fin[S[s]] = G;
         done[s] = 1;
@@ -1503,7 +1518,7 @@ static int run_cycle_batched(rsfde_ctx* h, const std::vector<int>& S, bool fp32,
     if (running == 0) return RSFDE_OK;
     j = jend;
     pending = -1;
-    chunk = 1;
+    chunk = need;
     if (j >= bp.kp.m) return RSFDE_OK;  // cannot happen: the last step of a cycle never runs on
     if (newly) CK(hipMemcpyAsync(h->dmask, h->pmask, ns * sizeof(int), hipMemcpyHostToDevice, h->stream));
   }
@@ -1803,7 +1818,7 @@ static int autotune(rsfde_ctx* h, Inst& I) {
             continue;
           }
         }
-        // variants interleaved over three rounds, each timing two launches whose
+        // variants interleaved over five rounds, each timing four launches whose
         // inputs and outputs rotate over the four temporaries (inputs are not
         // left cache-resident by the previous launch); the best round counts
         float tbest[RSFDE_PASS_VARIANTS];
@@ -1814,15 +1829,15 @@ static int autotune(rsfde_ctx* h, Inst& I) {
           have[v] = nt > 0;
           tbest[v] = 1e30f;
         }
-        for (int rep = 0; rep < 3 && status == RSFDE_OK; ++rep) {
+        for (int rep = 0; rep < 5 && status == RSFDE_OK; ++rep) {
           for (int v = 0; v < RSFDE_PASS_VARIANTS && status == RSFDE_OK; ++v) {
             if (!have[v]) continue;
             I.var[ax][fp][cls] = v;
             PassArgs t = mk_pass(I, ax, op, fp == 1);
             t.flags = flags;
             hipError_t e = hipEventRecord(e0, h->stream);
-            for (int r = 0; r < 2 && e == hipSuccess; ++r) {
-              const int k = 2 * rep + r + v;
+            for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+              const int k = rep + r + v;
               t.in_c = I.tmp[k & 3];
               t.in_a = I.tmp[(k + 1) & 3];
               t.out_a = I.tmp[(k + 2) & 3];
@@ -1841,15 +1856,16 @@ static int autotune(rsfde_ctx* h, Inst& I) {
             if (ms < tbest[v]) tbest[v] = ms;
           }
         }
-        // the default plan's widest tile unless another variant is 3 % faster
+        // the default plan's widest tile unless another tile is 3 % faster or the
+        // alternative plan 5 % faster (a plan change moves the rounding as well)
         int bestv = 0;
         for (int v = 1; v < RSFDE_PASS_VARIANTS; ++v)
-          if (have[v] && tbest[v] < tbest[bestv] * 0.97f) bestv = v;
+          if (have[v] && tbest[v] < tbest[bestv] * (v >= 3 && bestv < 3 ? 0.95f : 0.97f)) bestv = v;
         if (verbose) {
           fprintf(stderr, "rsfde autotune: %s axis %d %s %s pass, L %d:", arch, ax,
                   fp ? "fp32" : "fp64", cls ? "transform" : "operator", L);
           for (int v = 0; v < RSFDE_PASS_VARIANTS; ++v)
-            if (have[v]) fprintf(stderr, " v%d %.1f", v, 500.f * tbest[v]);
+            if (have[v]) fprintf(stderr, " v%d %.1f", v, 250.f * tbest[v]);
           fprintf(stderr, " us per launch -> variant %d\n", bestv);
         }
         I.var[ax][fp][cls] = bestv;
