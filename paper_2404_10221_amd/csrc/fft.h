@@ -97,8 +97,8 @@ template <int L> struct StageNs<L, 0> { static constexpr int value = 1; };
 // Twiddles W_L^m, m < L, from a half-length table in LDS: W_L^{m + L/2} = -W_L^m,
 // so entries m < L/2 suffice.  The table carries the same one-slot-per-256-byte
 // padding as the sequences, which spreads the strided twiddle reads of the last
-// stages over the banks.  Keeping twiddles in LDS instead of registers leaves
-// the registers to the butterflies and the batched global loads.
+// stages over the banks.  Used for the plans whose per-thread twiddles would take
+// too many registers (TwReg below) and by the setup and Strang kernels.
 template <typename R, int L>
 struct TwHalf {
   static constexpr int H = plan_len(L) / 2;
@@ -106,11 +106,40 @@ struct TwHalf {
   static constexpr int size = H + H / BS;
   const cpx<R>* tab;
   __device__ __forceinline__ static constexpr int pos(int m) { return m + m / BS; }
-  template <int S>
-  __device__ __forceinline__ cpx<R> get(int, int, int m) const {
+  __device__ __forceinline__ cpx<R> get(int m) const {
     const bool hi = m >= H;
     const cpx<R> w = tab[pos(hi ? m - H : m)];
     return hi ? -w : w;
+  }
+  // Twiddles w[r] = W^{r m} (conjugated for DIR = +1), r = 1..RAD-1, of one
+  // butterfly: the table values at r = 1, 2, 4 (and 8, 12 for RAD = 16) and
+  // products of two of them for the rest.  Three LDS reads instead of seven for
+  // radix 8, five instead of fifteen for radix 16; every power is at most two
+  // roundings from exact.  (S, B: stage and butterfly of the thread, unused here.)
+  template <int RAD, int DIR, int S, int B>
+  __device__ __forceinline__ void powers(int m, cpx<R>* w) const {
+    static_assert(RAD == 2 || RAD == 3 || RAD == 4 || RAD == 8 || RAD == 16, "unsupported radix");
+    auto rd = [&](int mm) {
+      cpx<R> x = get(mm);
+      if (DIR > 0) x.y = -x.y;
+      return x;
+    };
+    w[1] = rd(m);
+    if constexpr (RAD >= 3) w[2] = rd(2 * m);
+    if constexpr (RAD >= 4) w[3] = cmul(w[2], w[1]);
+    if constexpr (RAD >= 8) {
+      w[4] = rd(4 * m);
+#pragma unroll
+      for (int r = 5; r < 8; ++r) w[r] = cmul(w[4], w[r - 4]);
+    }
+    if constexpr (RAD == 16) {
+      w[8] = rd(8 * m);
+      w[12] = rd(12 * m);
+#pragma unroll
+      for (int r = 9; r < 12; ++r) w[r] = cmul(w[8], w[r - 8]);
+#pragma unroll
+      for (int r = 13; r < 16; ++r) w[r] = cmul(w[12], w[r - 12]);
+    }
   }
 };
 
@@ -254,36 +283,6 @@ __device__ __forceinline__ void dft(cpx<R>* v) {
   else static_assert(RAD == 2, "unsupported radix");
 }
 
-// Twiddles w[r] = W^{r m} (conjugated for DIR = +1), r = 1..RAD-1, of one butterfly:
-// the table values at r = 1, 2, 4 (and 8, 12 for RAD = 16) and products of two of
-// them for the rest.  Three LDS reads instead of seven for radix 8, five instead of
-// fifteen for radix 16; every power is at most two roundings from exact.
-template <typename R, int RAD, int DIR, int S, typename TW>
-__device__ __forceinline__ void tw_powers(const TW& tw, int m, cpx<R>* w) {
-  static_assert(RAD == 2 || RAD == 3 || RAD == 4 || RAD == 8 || RAD == 16, "unsupported radix");
-  auto rd = [&](int mm) {
-    cpx<R> x = tw.template get<S>(0, 0, mm);
-    if (DIR > 0) x.y = -x.y;
-    return x;
-  };
-  w[1] = rd(m);
-  if constexpr (RAD >= 3) w[2] = rd(2 * m);
-  if constexpr (RAD >= 4) w[3] = cmul(w[2], w[1]);
-  if constexpr (RAD >= 8) {
-    w[4] = rd(4 * m);
-#pragma unroll
-    for (int r = 5; r < 8; ++r) w[r] = cmul(w[4], w[r - 4]);
-  }
-  if constexpr (RAD == 16) {
-    w[8] = rd(8 * m);
-    w[12] = rd(12 * m);
-#pragma unroll
-    for (int r = 9; r < 12; ++r) w[r] = cmul(w[8], w[r - 8]);
-#pragma unroll
-    for (int r = 13; r < 16; ++r) w[r] = cmul(w[12], w[r - 12]);
-  }
-}
-
 // Barrier inside one transform.  When the T threads of a transform lie in one
 // wavefront (T divides 64), that wavefront's LDS accesses are performed in
 // program order, so a wavefront-scope fence and a wave barrier (which only stops
@@ -319,6 +318,85 @@ struct StageGeom {
   static constexpr int slot(int m) { return (m % NB) * RAD + m / NB; }
 };
 
+// Twiddles held in registers: per stage S >= 1 and per butterfly of the thread,
+// the base twiddle W_L^m of that butterfly (m = (j mod Ns) L/(Ns R), j = t + b T),
+// loaded once per kernel from the half table in global memory.  The powers come
+// from it by squaring and products: w2 = w1^2, w4 = w2^2, w8 = w4^2 and
+// w_{a+b} = w_a w_b for the rest, at most about a dozen roundings from exact for
+// radix 16 (against 2^-52 per rounding, far below the transforms' own error
+// growth).  When T is a multiple of Ns every butterfly of the thread shares one
+// base.  No LDS table and no LDS reads: the table costs 8 KB (L = 1024, FP64) to
+// 16 KB (L = 2048) per workgroup and its reads hit bank conflicts in the early
+// stages, where the exponents step by large strides.
+template <typename R, int L>
+struct TwReg {
+  using P = FftPlan<L>;
+  template <int S>
+  static constexpr int nb() {
+    if constexpr (S == 0 || S >= P::NS) {
+      return 0;
+    } else {
+      using G = StageGeom<R, L, S>;
+      return G::T % G::Ns == 0 ? 1 : G::NB;
+    }
+  }
+  template <int S>
+  static constexpr int off() {
+    if constexpr (S == 0) return 0;
+    else return off<S - 1>() + nb<S - 1>();
+  }
+  static constexpr int count = off<P::NS>();
+  cpx<R> base[count > 0 ? count : 1];
+
+  // (the table holds W_L^m for m < L/2, and every base exponent is below L/R)
+  __device__ __forceinline__ void load(const cpx<R>* __restrict__ tab, int t) {
+    static_for<P::NS>([&](auto sq) {
+      constexpr int S = decltype(sq)::value;
+      if constexpr (nb<S>() > 0) {
+        using G = StageGeom<R, L, S>;
+        constexpr int step = plan_len(L) / (G::Ns * G::RAD);
+        static_for<nb<S>()>([&](auto bq) {
+          constexpr int b = decltype(bq)::value;
+          base[off<S>() + b] = tab[((t + b * G::T) % G::Ns) * step];
+        });
+      }
+    });
+  }
+
+  template <int RAD, int DIR, int S, int B>
+  __device__ __forceinline__ void powers(int, cpx<R>* w) const {
+    static_assert(RAD == 2 || RAD == 3 || RAD == 4 || RAD == 8 || RAD == 16, "unsupported radix");
+    constexpr int bi = off<S>() + (nb<S>() == 1 ? 0 : B);
+    cpx<R> w1 = base[bi];
+    // (an empty asm that the compiler must assume changes w1: without it the
+    // powers, pure functions of the bases, are hoisted to the kernel start and
+    // shared by every transform, which keeps ~7 complex values per stage live)
+    asm volatile("" : "+v"(w1.x), "+v"(w1.y));
+    if (DIR > 0) w1.y = -w1.y;
+    auto sq = [](cpx<R> a) { return cpx<R>{(a.x - a.y) * (a.x + a.y), (R)2 * a.x * a.y}; };
+    w[1] = w1;
+    if constexpr (RAD >= 3) w[2] = sq(w1);
+    if constexpr (RAD >= 4) w[3] = cmul(w[2], w1);
+    if constexpr (RAD >= 8) {
+      w[4] = sq(w[2]);
+#pragma unroll
+      for (int r = 5; r < 8; ++r) w[r] = cmul(w[4], w[r - 4]);
+    }
+    if constexpr (RAD == 16) {
+      w[8] = sq(w[4]);
+#pragma unroll
+      for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    }
+  }
+};
+
+// Register twiddles where they cost at most 6 complex values per thread (the
+// 2^p plans of radix 8 and 16 up to 4096 points); the LDS table otherwise.
+template <typename R, int L>
+struct TwUseReg {
+  static constexpr bool value = TwReg<R, L>::count <= 6;
+};
+
 // (slots r >= rmax are set to zero instead of read)
 template <typename R, int L, int S>
 __device__ __forceinline__ void stage_read(const LdsSeq<R, L> buf, int t, cpx<R>* v,
@@ -344,19 +422,19 @@ template <typename R, int L, int DIR, int S, typename TW>
 __device__ __forceinline__ void stage_math(int t, const TW& tw, cpx<R>* v) {
   using G = StageGeom<R, L, S>;
   constexpr int RAD = G::RAD, Ns = G::Ns;
-#pragma unroll
-  for (int b = 0; b < G::NB; ++b) {
+  static_for<G::NB>([&](auto bq) {
+    constexpr int b = decltype(bq)::value;
     const int j = t + b * G::T;
     if constexpr (Ns > 1) {
       const int k = j % Ns;
       constexpr int step = plan_len(L) / (Ns * RAD);
       cpx<R> w[RAD];
-      tw_powers<R, RAD, DIR, S>(tw, k * step, w);
+      tw.template powers<RAD, DIR, S, b>(k * step, w);
 #pragma unroll
       for (int r = 1; r < RAD; ++r) v[b * RAD + r] = cmul(v[b * RAD + r], w[r]);
     }
     dft<R, RAD, DIR>(&v[b * RAD]);
-  }
+  });
 }
 
 template <typename R, int L, int S>
@@ -403,7 +481,7 @@ __device__ __forceinline__ void fft_stages(const LdsSeq<R, L> buf, int t, const 
 
 // Full transform of the length-L sequence in `buf` (all threads of the
 // workgroup must call it together: it contains barriers).  `tw` is a TwReg or
-// TwLds twiddle provider.
+// TwHalf twiddle provider.
 template <typename R, int L, int DIR, typename TW>
 __device__ __forceinline__ void fft_lds(const LdsSeq<R, L> buf, int t, const TW& tw) {
   fft_stages<R, L, DIR, 0>(buf, t, tw);
@@ -427,9 +505,9 @@ __device__ __forceinline__ void fft_mid_stages(const LdsSeq<R, L> buf, int t, co
 // t + T m of the sequence (m < E), on exit c[m] is element t + T m of its
 // transform.  Those are the first stage's inputs and the last stage's outputs
 // of thread t, so only the stages in between go through LDS.  FRESH: the LDS
-// sequence has not been read since the last workgroup barrier, and the twiddle
-// table still needs one (taken after the first stage's writes); otherwise a
-// previous register transform of the same threads has just read it.
+// sequence has not been read since the last workgroup barrier, and an LDS
+// twiddle table still needs one (taken after the first stage's writes);
+// otherwise a previous register transform of the same threads has just read it.
 template <typename R, int L, int DIR, bool FRESH, typename TW>
 __device__ __forceinline__ void fft_regs(const LdsSeq<R, L> buf, int t, const TW& tw, cpx<R>* c) {
   using P = FftPlan<L>;

@@ -120,10 +120,12 @@ struct PassShape {
   static constexpr int T = FftPlan<L>::T;
   // (sized for the largest pitch, S + M - 1)
   static constexpr int bytes_per_fft = (LdsSeq<R, L>::size + LdsPitch<R, L, 1>::M) * (int)sizeof(cpx<R>);
-  // LDS left for the transforms: 160 KB minus the twiddle table, the circulant spectrum
-  // and 2 KB for the small shared arrays (block sums, Givens column, y)
-  static constexpr int cap =
-      160 * 1024 - TwHalf<R, L>::size * (int)sizeof(cpx<R>) - plan_len(L) * (int)sizeof(R) - 2048;
+  // LDS left for the transforms: 160 KB minus the twiddle table (plans without
+  // register twiddles), the circulant spectrum and 2 KB for the small shared arrays
+  // (block sums, Givens column, y)
+  static constexpr int cap = 160 * 1024 -
+                             (TwUseReg<R, L>::value ? 0 : TwHalf<R, L>::size * (int)sizeof(cpx<R>)) -
+                             plan_len(L) * (int)sizeof(R) - 2048;
   static constexpr int want = 512 / T > 1 ? 512 / T : 1;
   static constexpr int lim = cap / bytes_per_fft;
   static constexpr int F0a = want < lim ? want : lim;
@@ -146,14 +148,16 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   constexpr int T = P::T, E = P::E, NT = F * T, PT = 2 * F;
   constexpr int LP = LdsPitch<R, L, F>::value;
   constexpr int NE = STRIDED ? E : E / 2;  // element slots per thread
+  constexpr bool twreg = TwUseReg<R, L>::value;
   __shared__ cpx<R> lds[F * LP];
-  __shared__ cpx<R> twl[TwHalf<R, L>::size];
+  __shared__ cpx<R> twl[twreg ? 1 : TwHalf<R, L>::size];
   // circulant spectrum / L (operator passes), or the axis-0 tables of OP_DSD;
   // not used by the strided sine-transform kernel
   __shared__ R chs[STRIDED && MODE == PK_TR ? 1 : plan_len(L)];
 
   const int tid = threadIdx.x;
-  const TwHalf<R, L> tw{twl};
+  std::conditional_t<twreg, TwReg<R, L>, TwHalf<R, L>> tw;
+  if constexpr (!twreg) tw.tab = twl;
   const int f = tid / T;
   const int t = tid - f * T;
   const LdsSeq<R, L> buf{lds + f * LP};
@@ -278,8 +282,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   // (the 1/mu scaling runs along the contiguous axis only)
   const bool is_dsd = !STRIDED && !mv_op && a.op == OP_DSD;
   R lt[CH];
-  R twr[TwFill<R, L, NT>::C], twi[TwFill<R, L, NT>::C];
-  tw_load<R, L, NT>(twr, twi, (const cpx<R>*)a.tw, tid);
+  R twr[twreg ? 1 : TwFill<R, L, NT>::C], twi[twreg ? 1 : TwFill<R, L, NT>::C];
+  if constexpr (twreg) tw.load((const cpx<R>*)a.tw, t);
+  else tw_load<R, L, NT>(twr, twi, (const cpx<R>*)a.tw, tid);
   R rl[2][2], rw[2][2];  // [pencil of the pair][axis 1, 2]: lambda and eta q / lambda
   R ebv = (R)0;
   if (mv_op) {
@@ -332,7 +337,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   }
   const R bd = (R)a.bd, bo = (R)a.bo, eta = (R)a.eta;
   const R* __restrict__ chat = chs;
-  tw_store<R, L, NT>(twr, twi, twl, tid);
+  if constexpr (!twreg) tw_store<R, L, NT>(twr, twi, twl, tid);
   if (mv_op || is_dsd) {
     static_for<CH>([&](auto q) {
       const int k = tid + q.value * NT;
