@@ -71,19 +71,48 @@ RSFDE_ALT_PLAN(4096, 8, 8, 8, 8, 8)
 
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 
-// One transform's sequence in LDS, with one pad slot after every 256 bytes.
-// The LDS of gfx950 serves 256 bytes (64 four-byte banks) per pass; the
-// Stockham writes of the early stages step through a sequence with strides of R
-// elements, which lands a whole wavefront on a few banks.  The pad shifts each
-// 256-byte row by one element, spreading those writes over every bank, while
-// runs of consecutive elements stay conflict-free.  The layout also keeps the
-// per-element offsets of a butterfly compile-time constants (see fft_stage).
+// Layout of one transform's sequence in LDS.  Measured on gfx950 (rocprofv3 LDS
+// bank-conflict counters on probe kernels): a wave-wide 16-byte store is served
+// eight lanes at a time over 32 four-byte banks, so eight consecutive lanes
+// writing the same 16-byte column conflict; a 16-byte load is conflict-free as
+// long as every 128-byte row that the lanes touch is read whole (rows in any
+// order, elements permuted inside a row), and takes about twice as long once the
+// lane groups are offset against the rows.
+//
+// FP64 sequences of 2048 and 4096 points whose plan is all radix 8 (and 4, 2)
+// are stored with an XOR swizzle inside each 128-byte row: element i sits at
+// slot i ^ ((i >> 3) & 7).  Unit-stride reads then read whole rows, and the
+// Stockham writes of the first stages (element 8 t + r of thread t, stride 8)
+// land eight consecutive lanes in eight columns.  The other sequences keep one
+// pad slot after every 256 bytes, which spreads strided writes but offsets
+// unit-stride reads: with 512 and 1024 points, or a radix-16 plan, the swizzle's
+// per-element slot arithmetic pushed the operator passes past their register
+// budget (spills, or one wave per SIMD), which cost more than the conflicts.
+template <int L>
+struct LdsSwz {
+  using P = FftPlan<L>;
+  static constexpr bool pow2() {
+    for (int k = 0; k < P::NS; ++k)
+      if (P::R[k] == 3) return false;
+    return true;
+  }
+  static constexpr int K = pow2() && P::Lv >= 2048 && P::R[0] == 8 ? 3 : 0;
+};
+
 template <typename R, int L>
 struct LdsSeq {
   static constexpr int BS = 256 / (int)sizeof(cpx<R>);  // elements per 256-byte row
-  static constexpr int size = plan_len(L) + plan_len(L) / BS;  // slots of one sequence
+  static constexpr int K = sizeof(R) == 8 ? LdsSwz<L>::K : 0;
+  static constexpr bool XS = K > 0;  // swizzled (else padded) layout
+  static constexpr int size = XS ? plan_len(L) : plan_len(L) + plan_len(L) / BS;  // slots
+  // pos(i + d) = pos(i) + shift(d) for every i when d is a multiple of FOLD
+  static constexpr int FOLD = XS ? (8 << K) : BS;
   cpx<R>* p;
-  __device__ __forceinline__ static constexpr int pos(int i) { return i + i / BS; }
+  __device__ __forceinline__ static constexpr int pos(int i) {
+    if constexpr (XS) return i ^ ((i >> K) & 7);
+    else return i + i / BS;
+  }
+  __device__ __forceinline__ static constexpr int shift(int d) { return XS ? d : d + d / BS; }
   __device__ __forceinline__ cpx<R>& operator[](int i) const { return p[pos(i)]; }
   // R-typed view of component c of element i
   __device__ __forceinline__ R& comp(int i, int c) const { return ((R*)(p + pos(i)))[c]; }
@@ -403,10 +432,10 @@ __device__ __forceinline__ void stage_read(const LdsSeq<R, L> buf, int t, cpx<R>
                                            const int rmax = StageGeom<R, L, S>::RAD) {
   using G = StageGeom<R, L, S>;
   using Q = LdsSeq<R, L>;
-  constexpr int BS = Q::BS, LR = G::LR;
-  // Reads x[j + r L/R]: when L/R is a whole number of rows, pos(j + r L/R) =
-  // pos(j) + r (L/R + L/(R BS)), a constant offset per r.
-  constexpr bool rd_fold = LR % BS == 0;
+  constexpr int LR = G::LR;
+  // Reads x[j + r L/R]: when L/R is a multiple of the layout's fold distance,
+  // pos(j + r L/R) = pos(j) + shift(r L/R), a constant offset per r.
+  constexpr bool rd_fold = LR % Q::FOLD == 0;
 #pragma unroll
   for (int b = 0; b < G::NB; ++b) {
     const int j = t + b * G::T;
@@ -414,7 +443,7 @@ __device__ __forceinline__ void stage_read(const LdsSeq<R, L> buf, int t, cpx<R>
 #pragma unroll
     for (int r = 0; r < G::RAD; ++r)
       v[b * G::RAD + r] = r >= rmax ? cpx<R>{0, 0}
-                                    : (rd_fold ? buf.p[pj + r * (LR + LR / BS)] : buf[j + r * LR]);
+                                    : (rd_fold ? buf.p[pj + Q::shift(r * LR)] : buf[j + r * LR]);
   }
 }
 
@@ -442,11 +471,14 @@ __device__ __forceinline__ void stage_write(const LdsSeq<R, L> buf, int t, const
   using G = StageGeom<R, L, S>;
   using Q = LdsSeq<R, L>;
   constexpr int BS = Q::BS, RAD = G::RAD, Ns = G::Ns;
-  // Writes y[base + r Ns], base = (j/Ns) Ns R + j mod Ns: the row of base + r Ns
-  // is the row of base plus (r Ns)/BS when Ns is a multiple of BS, or Ns divides
-  // BS and Ns R is a multiple or a divisor of BS (no carry out of the row).
+  // Writes y[base + r Ns], base = (j/Ns) Ns R + j mod Ns.  Swizzled layout: a
+  // constant offset r Ns when Ns is a multiple of the fold distance.  Padded
+  // layout: the row of base + r Ns is the row of base plus (r Ns)/BS when Ns is a
+  // multiple of BS, or Ns divides BS and Ns R is a multiple or a divisor of BS (no
+  // carry out of the row).
   constexpr bool wr_fold =
-      Ns % BS == 0 || (BS % Ns == 0 && ((Ns * RAD) % BS == 0 || BS % (Ns * RAD) == 0));
+      Q::XS ? Ns % Q::FOLD == 0
+            : (Ns % BS == 0 || (BS % Ns == 0 && ((Ns * RAD) % BS == 0 || BS % (Ns * RAD) == 0)));
 #pragma unroll
   for (int b = 0; b < G::NB; ++b) {
     const int j = t + b * G::T;
@@ -455,7 +487,7 @@ __device__ __forceinline__ void stage_write(const LdsSeq<R, L> buf, int t, const
     const int pb = Q::pos(base);
 #pragma unroll
     for (int r = 0; r < RAD; ++r) {
-      if constexpr (wr_fold) buf.p[pb + r * Ns + (r * Ns) / BS] = v[b * RAD + r];
+      if constexpr (wr_fold) buf.p[pb + (Q::XS ? r * Ns : r * Ns + (r * Ns) / BS)] = v[b * RAD + r];
       else buf[base + r * Ns] = v[b * RAD + r];
     }
   }
