@@ -414,7 +414,13 @@ def main():
             "launches": "launches that exited on the status word past the end of their "
                         "GMRES cycle are left out",
         },
-        "kernel_time_share_warmup": {k: round(v[1], 4) for k, v in tot.items()},
+        # every kernel class over the fully timed warm-up: launches that did work,
+        # total and average time, and the HBM fraction of its algorithmic bytes
+        "kernel_classes_warmup": {
+            k: {"launches": v[0], "ms": round(v[1], 4),
+                "avg_us": round(1e3 * v[1] / v[0], 2),
+                "frac": round((v[2] / v[0]) / ((v[1] / v[0]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            for k, v in tot.items() if v[0] > 0 and v[1] > 0},
     }
 
     def rel(xs, ys):
