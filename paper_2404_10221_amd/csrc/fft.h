@@ -74,48 +74,50 @@ constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 // Layout of one transform's sequence in LDS.  Measured on gfx950 (rocprofv3 LDS
 // bank-conflict counters on probe kernels): a wave-wide 16-byte store is served
 // eight lanes at a time over 32 four-byte banks, so eight consecutive lanes
-// writing the same 16-byte column conflict; a 16-byte load is conflict-free as
-// long as every 128-byte row that the lanes touch is read whole (rows in any
-// order, elements permuted inside a row), and takes about twice as long once the
-// lane groups are offset against the rows.
+// writing the same 16-byte column conflict; a 16-byte load at unit stride is
+// conflict-free, and costs about twice as much once the 16- or 8-lane groups of
+// a 32-lane half are offset against each other (as a pad slot every 256 bytes
+// does).
 //
-// FP64 sequences of 2048 and 4096 points whose plan is all radix 8 (and 4, 2)
-// are stored with an XOR swizzle inside each 128-byte row: element i sits at
-// slot i ^ ((i >> 3) & 7).  Unit-stride reads then read whole rows, and the
-// Stockham writes of the first stages (element 8 t + r of thread t, stride 8)
-// land eight consecutive lanes in eight columns.  The other sequences keep one
-// pad slot after every 256 bytes, which spreads strided writes but offsets
-// unit-stride reads: with 512 and 1024 points, or a radix-16 plan, the swizzle's
-// per-element slot arithmetic pushed the operator passes past their register
-// budget (spills, or one wave per SIMD), which cost more than the conflicts.
-template <int L>
-struct LdsSwz {
-  using P = FftPlan<L>;
-  static constexpr bool pow2() {
-    for (int k = 0; k < P::NS; ++k)
-      if (P::R[k] == 3) return false;
-    return true;
-  }
-  static constexpr int K = pow2() && P::Lv >= 2048 && P::R[0] == 8 ? 3 : 0;
-};
-
+// FP64 sequences are therefore stored plainly (element i in slot i): every
+// unit-stride access of the passes (loads, stencils, stage reads, stores) is
+// conflict-free and its offsets are compile-time constants.  The one strided
+// access is the first Stockham stage's write (element R t + r from thread t, a
+// stride of R slots); between the first and the second stage only, the sequence
+// is XOR-swizzled inside 128-byte rows, slot(i) = i ^ ((i >> K) & 7) with
+// 2^K = min(R, 8) (StageSwz), which spreads eight consecutive lanes over eight
+// columns (four for R = 16) and keeps the second stage's unit-stride reads
+// whole-row, at offsets that fold into constants (K = 4 for R = 16 would not fold
+// at 1024 points, and the per-read slot arithmetic cost a wave per SIMD).  FP32
+// sequences (8-byte elements) keep one pad slot after every 256 bytes.
 template <typename R, int L>
 struct LdsSeq {
   static constexpr int BS = 256 / (int)sizeof(cpx<R>);  // elements per 256-byte row
-  static constexpr int K = sizeof(R) == 8 ? LdsSwz<L>::K : 0;
-  static constexpr bool XS = K > 0;  // swizzled (else padded) layout
-  static constexpr int size = XS ? plan_len(L) : plan_len(L) + plan_len(L) / BS;  // slots
+  static constexpr bool PAD = sizeof(R) != 8;            // padded (FP32) or plain layout
+  static constexpr int size = PAD ? plan_len(L) + plan_len(L) / BS : plan_len(L);  // slots
   // pos(i + d) = pos(i) + shift(d) for every i when d is a multiple of FOLD
-  static constexpr int FOLD = XS ? (8 << K) : BS;
+  static constexpr int FOLD = PAD ? BS : 1;
   cpx<R>* p;
-  __device__ __forceinline__ static constexpr int pos(int i) {
-    if constexpr (XS) return i ^ ((i >> K) & 7);
-    else return i + i / BS;
-  }
-  __device__ __forceinline__ static constexpr int shift(int d) { return XS ? d : d + d / BS; }
+  __device__ __forceinline__ static constexpr int pos(int i) { return PAD ? i + i / BS : i; }
+  __device__ __forceinline__ static constexpr int shift(int d) { return PAD ? d + d / BS : d; }
   __device__ __forceinline__ cpx<R>& operator[](int i) const { return p[pos(i)]; }
   // R-typed view of component c of element i
   __device__ __forceinline__ R& comp(int i, int c) const { return ((R*)(p + pos(i)))[c]; }
+};
+
+// Swizzle of the sequence between the first and the second Stockham stage (plain
+// FP64 layouts whose first radix is a power of two and that have a second
+// stage).  i ^ ((i >> K) & 7) is a bijection: bit b < 3 is XORed with bit b + K,
+// which is recovered first from the top.
+template <typename R, int L>
+struct StageSwz {
+  using P = FftPlan<L>;
+  static constexpr int R0 = P::R[0];
+  static constexpr int K = R0 == 2 ? 1 : R0 == 4 ? 2 : (R0 == 8 || R0 == 16) ? 3 : 0;
+  static constexpr bool on = !LdsSeq<R, L>::PAD && K > 0 && P::NS > 1;
+  // slot(i + d) = slot(i) + d for every i when d is a multiple of FOLD
+  static constexpr int FOLD = 8 << K;
+  __device__ __forceinline__ static constexpr int slot(int i) { return on ? i ^ ((i >> K) & 7) : i; }
 };
 
 template <int L, int S> struct StageNs {
@@ -432,18 +434,26 @@ __device__ __forceinline__ void stage_read(const LdsSeq<R, L> buf, int t, cpx<R>
                                            const int rmax = StageGeom<R, L, S>::RAD) {
   using G = StageGeom<R, L, S>;
   using Q = LdsSeq<R, L>;
+  using W = StageSwz<R, L>;
   constexpr int LR = G::LR;
+  constexpr bool swz = S == 1 && W::on;  // reads the first stage's swizzled output
   // Reads x[j + r L/R]: when L/R is a multiple of the layout's fold distance,
-  // pos(j + r L/R) = pos(j) + shift(r L/R), a constant offset per r.
-  constexpr bool rd_fold = LR % Q::FOLD == 0;
+  // the slot of j + r L/R is the slot of j plus a constant offset per r.
+  constexpr bool rd_fold = swz ? LR % W::FOLD == 0 : LR % Q::FOLD == 0;
 #pragma unroll
   for (int b = 0; b < G::NB; ++b) {
     const int j = t + b * G::T;
-    const int pj = Q::pos(j);
+    const int pj = swz ? W::slot(j) : Q::pos(j);
 #pragma unroll
-    for (int r = 0; r < G::RAD; ++r)
-      v[b * G::RAD + r] = r >= rmax ? cpx<R>{0, 0}
-                                    : (rd_fold ? buf.p[pj + Q::shift(r * LR)] : buf[j + r * LR]);
+    for (int r = 0; r < G::RAD; ++r) {
+      cpx<R> x{0, 0};
+      if (r < rmax) {
+        if constexpr (rd_fold) x = buf.p[pj + (swz ? r * LR : Q::shift(r * LR))];
+        else if constexpr (swz) x = buf.p[W::slot(j + r * LR)];
+        else x = buf[j + r * LR];
+      }
+      v[b * G::RAD + r] = x;
+    }
   }
 }
 
@@ -470,15 +480,25 @@ template <typename R, int L, int S>
 __device__ __forceinline__ void stage_write(const LdsSeq<R, L> buf, int t, const cpx<R>* v) {
   using G = StageGeom<R, L, S>;
   using Q = LdsSeq<R, L>;
+  using W = StageSwz<R, L>;
   constexpr int BS = Q::BS, RAD = G::RAD, Ns = G::Ns;
-  // Writes y[base + r Ns], base = (j/Ns) Ns R + j mod Ns.  Swizzled layout: a
-  // constant offset r Ns when Ns is a multiple of the fold distance.  Padded
-  // layout: the row of base + r Ns is the row of base plus (r Ns)/BS when Ns is a
-  // multiple of BS, or Ns divides BS and Ns R is a multiple or a divisor of BS (no
-  // carry out of the row).
+  if constexpr (S == 0 && W::on) {
+    // first stage, swizzled: elements R j + r (the low bits of R j are zero, so
+    // the slot arithmetic reduces to an XOR with a constant per r)
+#pragma unroll
+    for (int b = 0; b < G::NB; ++b) {
+      const int base = (t + b * G::T) * RAD;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf.p[W::slot(base + r)] = v[b * RAD + r];
+    }
+    return;
+  }
+  // Writes y[base + r Ns], base = (j/Ns) Ns R + j mod Ns.  Plain layout: a
+  // constant offset r Ns.  Padded layout: the row of base + r Ns is the row of
+  // base plus (r Ns)/BS when Ns is a multiple of BS, or Ns divides BS and Ns R is
+  // a multiple or a divisor of BS (no carry out of the row).
   constexpr bool wr_fold =
-      Q::XS ? Ns % Q::FOLD == 0
-            : (Ns % BS == 0 || (BS % Ns == 0 && ((Ns * RAD) % BS == 0 || BS % (Ns * RAD) == 0)));
+      !Q::PAD || (Ns % BS == 0 || (BS % Ns == 0 && ((Ns * RAD) % BS == 0 || BS % (Ns * RAD) == 0)));
 #pragma unroll
   for (int b = 0; b < G::NB; ++b) {
     const int j = t + b * G::T;
@@ -487,7 +507,7 @@ __device__ __forceinline__ void stage_write(const LdsSeq<R, L> buf, int t, const
     const int pb = Q::pos(base);
 #pragma unroll
     for (int r = 0; r < RAD; ++r) {
-      if constexpr (wr_fold) buf.p[pb + (Q::XS ? r * Ns : r * Ns + (r * Ns) / BS)] = v[b * RAD + r];
+      if constexpr (wr_fold) buf.p[pb + (Q::PAD ? r * Ns + (r * Ns) / BS : r * Ns)] = v[b * RAD + r];
       else buf[base + r * Ns] = v[b * RAD + r];
     }
   }
