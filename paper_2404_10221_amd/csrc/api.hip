@@ -211,6 +211,8 @@ struct Inst {
   rsfde_params p{};
   int d = 0;
   int64_t n = 0, nclo = 0, ldv = 0;
+  int nb = 1;  // blocks of the Krylov sweeps and norms (kry_blocks, or kry_blocks_many on
+               // handles of several instances, batched or not, so both agree bit for bit)
   Axis ax[3];
   double *e = nullptr, *f = nullptr, *F = nullptr, *b = nullptr, *V = nullptr;
   const double* ecur = nullptr;  // e of the current step (the caller's buffer or e)
@@ -979,7 +981,7 @@ static void graphs_clear(std::vector<hipGraphExec_t>& cache) {
 
 static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* S) {
   const int m = I.p.restart;
-  const int nb = kry_blocks(I.n);
+  const int nb = I.nb;
   int j = 0;
   int pending = -1;  // step the next first pass must resolve (-1: already resolved)
   int chunk = std::max(1, std::min(m, I.k_prev));
@@ -1010,6 +1012,7 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
         ka.pc = I.pk[2];
         ka.j = jj;
         ka.m = m;
+        ka.nb = nb;
         const double vb = 8.0 * (double)I.n;
         CKS(timed_launch(h, RSFDE_K_DOTS, vb * (jj + 2),
                          [&](hipEvent_t ea, hipEvent_t eb) { return kry_sweep(1, ka, h->stream, ea, eb); }));
@@ -1129,7 +1132,7 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
       CKS(need_b());
       CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
     }
-    CK(kry_cycle_init(I.V, I.n, I.st, I.partial, cyc == 0 ? 1 : 0, stop_rtol, inner_rtol,
+    CK(kry_cycle_init(I.V, I.n, I.nb, I.st, I.partial, cyc == 0 ? 1 : 0, stop_rtol, inner_rtol,
                       mixed ? 1 : 0, p.restart, h->stream));
     if (mixed && cyc == max_outer) {
       // final check only
@@ -1164,7 +1167,7 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
     // recompute z = M (b - A u) in FP64 from the returned u (V_0 is free here)
     CKS(need_b());
     CKS(run_chain(h, I, CH_RESID, false, u, nullptr, I.b, 1.0, I.V));
-    CK(kry_cycle_init(I.V, I.n, I.st, I.partial, 0, p.rtol, inner_rtol, 0, p.restart, h->stream));
+    CK(kry_cycle_init(I.V, I.n, I.nb, I.st, I.partial, 0, p.rtol, inner_rtol, 0, p.restart, h->stream));
     GmresSummary R;
     CKS(read_summary(h, I, &R));
     if (!std::isfinite(R.beta)) return RSFDE_E_NONFINITE;
@@ -1349,7 +1352,8 @@ static int plan_krylov(rsfde_ctx* h, int r, const std::vector<int>& S, double* c
     d.partial = I.partial;
     d.rtol = I.p.precision == RSFDE_MIXED ? outer_tol(I.p) : I.p.rtol;
     d.inner_rtol = inner_tol(I.p);
-    d.nb = kry_blocks(I.n);
+    d.k.nb = I.nb;
+    d.nb = I.nb;
     d.nbu = upd_blocks(I.n);
     d.mixed = I.p.precision == RSFDE_MIXED ? 1 : 0;
     desc.push_back(d);
@@ -1422,7 +1426,7 @@ static int build_plans(rsfde_ctx* h, int r, const std::vector<int>& S, double* c
     GmRes g;
     g.st = I.st;
     g.p3 = I.pk[2];
-    g.nb3 = kry_blocks(I.n);
+    g.nb3 = I.nb;
     g.j = 0;
     g.pend = -1;
     g.m = I.p.restart;
@@ -1650,7 +1654,7 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
       // the recomputed FP64 residual of each instance, one at a time (V_0 is free)
       Inst& I = h->inst[i];
       CKS(run_chain(h, I, CH_RESID, false, u[i], nullptr, I.b, 1.0, I.V));
-      CK(kry_cycle_init(I.V, I.n, I.st, I.partial, 0, I.p.rtol, inner_tol(I.p), 0, I.p.restart,
+      CK(kry_cycle_init(I.V, I.n, I.nb, I.st, I.partial, 0, I.p.rtol, inner_tol(I.p), 0, I.p.restart,
                         h->stream));
       GmresSummary R;
       CKS(read_summary(h, I, &R));
@@ -1942,6 +1946,7 @@ int rsfde_setup(const rsfde_params* p, int count, void* workspace, size_t bytes,
     Inst& I = h->inst[i];
     I.p = p[i];
     layout(I, B);
+    I.nb = count > 1 ? kry_blocks_many(I.n) : kry_blocks(I.n);
     double pscale = 1.0;
     int64_t inner = 1;
     for (int a = 0; a < I.d; ++a) {

@@ -71,6 +71,18 @@ inline int kry_blocks(int64_t n) {
   return (int)b;
 }
 
+// Blocks for an instance of a many-instance handle: at least 4096 entries per
+// block.  Every block of a sweep first reduces the previous sweep's partials and
+// forms the projection coefficients; with the single-instance count (one block
+// per 1024 entries) that prologue outweighed the vector work of the small
+// instances, and the batched launches already fill the GPU with many instances.
+inline int kry_blocks_many(int64_t n) {
+  int64_t b = (n + 4095) / 4096;
+  if (b > RSFDE_KRY_BLOCKS) b = RSFDE_KRY_BLOCKS;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
 // Pending-resolve descriptor carried by the first operator pass of a step and
 // by the update kernel.
 struct GmRes {
@@ -256,6 +268,7 @@ struct KryArgs {
   double* pc;         // sweep-3 partials
   int j;              // Arnoldi index (w = P^{-1} A v_j)
   int m;              // restart length
+  int nb;             // blocks of the sweeps (kry_blocks or kry_blocks_many)
 };
 
 // Blocks of the solution-update kernel for an n-vector.
@@ -273,7 +286,7 @@ struct KBatch {
   double* x;           // solution the update kernel adds V y to
   double* partial;     // cycle-start norm partials
   double rtol, inner_rtol;
-  int nb;              // blocks of this instance's sweeps and norm (kry_blocks(n))
+  int nb;              // blocks of this instance's sweeps and norm (KryArgs::nb)
   int nbu;             // blocks of this instance's update (upd_blocks(n))
   int mixed;
   int pad;
@@ -287,7 +300,7 @@ struct KLaunch {
 };
 
 // Launchers (krylov.hip)
-hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial, int first,
+hipError_t kry_cycle_init(double* v0, int64_t n, int nb, GmresState* st, double* partial, int first,
                           double rtol, double inner_rtol, int mixed, int m, hipStream_t s);
 // ea/eb: when non-null, HIP events stamped at the dispatch's start and end
 hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea = nullptr,

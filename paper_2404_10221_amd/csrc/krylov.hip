@@ -499,9 +499,8 @@ __global__ void k_state_reset(GmresState* st) {
 }
 
 // ---- launchers ---------------------------------------------------------------------------
-hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial, int first,
+hipError_t kry_cycle_init(double* v0, int64_t n, int nb, GmresState* st, double* partial, int first,
                           double rtol, double inner_rtol, int mixed, int m, hipStream_t s) {
-  const int nb = kry_blocks(n);
   hipLaunchKernelGGL(k_norm_part, dim3(nb), dim3(1024), 0, s, v0, n, partial);
   hipLaunchKernelGGL(k_cycle_init_fin, dim3(1), dim3(256), 0, s, partial, nb, st, first, rtol,
                      inner_rtol, mixed, m);
@@ -518,7 +517,7 @@ hipError_t kry_cycle_init(double* v0, int64_t n, GmresState* st, double* partial
 
 hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
   const int nv = a.j + 1;
-  const dim3 g(kry_blocks(a.n));
+  const dim3 g(a.nb);
   if (which == 1) {
     if (a.j >= 1 && 2 * nv <= 64) {
       KRY_SWEEP(k_sweepA, 1, 2 * nv, g, a, s);
