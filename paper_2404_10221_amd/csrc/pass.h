@@ -139,6 +139,24 @@ struct PassShape {
 // (two kernels, each with the registers of its own path).
 enum : int { PK_MV = 1, PK_TR = 2 };
 
+// Scale-phase factors of the two pencils of a packed pair, from g = mu / Lambda
+// and Lambda (lam0, lam1) of each pencil: ps/(Lambda g) = ps/mu for PM_BP_INV
+// (SQ false); for the two-sided forms (SQ true) ps/(Lambda sqrt g) =
+// ps/sqrt(Lambda mu) for PM_PH_BINV and ps/sqrt g = ps sqrt(Lambda/mu) for PM_PH.
+// One division for the pair: ps/(d0 d1) times d1 and d0.
+template <typename R, bool SQ>
+__device__ __forceinline__ void scale_pair(R g0, R g1, R lam0, R lam1, R ps, int pm, R& s0, R& s1) {
+  if constexpr (SQ) {
+    g0 = sqrt(g0);
+    g1 = sqrt(g1);
+  }
+  const R d0 = SQ && pm == PM_PH ? g0 : lam0 * g0;
+  const R d1 = SQ && pm == PM_PH ? g1 : lam1 * g1;
+  const R r = ps / (d0 * d1);
+  s0 = r * d1;
+  s1 = r * d0;
+}
+
 // The pass on one tile; `bid` is the workgroup's index within the pass (the
 // block index of a single-instance launch, the local index in a batched one).
 template <typename R, int L, int F, bool STRIDED, int MODE>
@@ -385,22 +403,25 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
         Lam[q] = ((R)1 * rl[q][0]) * rl[q][1];
         Sig[q] = ((R)0 + rw[q][0]) + rw[q][1];
       }
+      // (one loop per form, chosen by a uniform branch: the square roots of the
+      // two-sided factors are not computed, and then discarded, for the one-sided one)
+      auto scale = [&](auto sqc) {
+        constexpr bool SQ = decltype(sqc)::value;
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int p = t + (m % NE) * T;             // distance from 0 or from L/2
-        const bool live = p >= 1;
-        const int idx = live ? (m < NE ? p - 1 : N - p) : 0;  // sine index, < N
-        const R l0 = chs[idx], w0 = chs[N + idx];
-        R g0 = ebv + w0 + Sig[0], g1 = ebv + w0 + Sig[1];  // mu / Lambda
-        if (pm != PM_BP_INV) {
-          g0 = sqrt(g0);
-          g1 = sqrt(g1);
+        for (int m = 0; m < E; ++m) {
+          const int p = t + (m % NE) * T;             // distance from 0 or from L/2
+          const bool live = p >= 1;
+          const int idx = live ? (m < NE ? p - 1 : N - p) : 0;  // sine index, < N
+          const R l0 = chs[idx], w0 = chs[N + idx];
+          R s0, s1;
+          scale_pair<R, SQ>(ebv + w0 + Sig[0], ebv + w0 + Sig[1], Lam[0] * l0, Lam[1] * l0, ps,
+                            pm, s0, s1);
+          const cpx<R> Z = c[m];
+          c[m] = live ? cpx<R>{-Z.y * s0, Z.x * s1} : cpx<R>{0, 0};
         }
-        const R s0 = ps / (pm == PM_PH ? g0 : Lam[0] * l0 * g0);
-        const R s1 = ps / (pm == PM_PH ? g1 : Lam[1] * l0 * g1);
-        const cpx<R> Z = c[m];
-        c[m] = live ? cpx<R>{-Z.y * s0, Z.x * s1} : cpx<R>{0, 0};
-      }
+      };
+      if (pm == PM_BP_INV) scale(std::false_type{});
+      else scale(std::true_type{});
       fft_regs<R, L, -1, false>(buf, t, tw, c);
     }
     // 2 DST(x0) = -Im Z_k, 2 DST(x1) = Re Z_k at k = t + T i (1 <= k <= N)
@@ -693,22 +714,23 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
         l0v[i] = lam0[pc];
         w0v[i] = wq0[pc];
       }
+      auto scale = [&](auto sqc) {
+        constexpr bool SQ = decltype(sqc)::value;
 #pragma unroll
-      for (int i = 0; i < NE; ++i) {
-        const int p = t + i * T;
-        if (p < N) {
-          const cpx<R> Z = buf[p + 1];
-          const R l0 = l0v[i], w0 = w0v[i];
-          R g0 = eb + w0 + Sig[0], g1 = eb + w0 + Sig[1];  // mu / Lambda
-          if (pm != PM_BP_INV) {
-            g0 = sqrt(g0);
-            g1 = sqrt(g1);
+        for (int i = 0; i < NE; ++i) {
+          const int p = t + i * T;
+          if (p < N) {
+            const cpx<R> Z = buf[p + 1];
+            const R l0 = l0v[i], w0 = w0v[i];
+            R s0, s1;
+            scale_pair<R, SQ>(eb + w0 + Sig[0], eb + w0 + Sig[1], Lam[0] * l0, Lam[1] * l0, ps, pm,
+                              s0, s1);
+            ra[i] = cpx<R>{-Z.y * s0, Z.x * s1};
           }
-          const R s0 = ps / (pm == PM_PH ? g0 : Lam[0] * l0 * g0);
-          const R s1 = ps / (pm == PM_PH ? g1 : Lam[1] * l0 * g1);
-          ra[i] = cpx<R>{-Z.y * s0, Z.x * s1};
         }
-      }
+      };
+      if (pm == PM_BP_INV) scale(std::false_type{});
+      else scale(std::true_type{});
       __syncthreads();
       if (t == 0) {
         buf[0] = cpx<R>{0, 0};
