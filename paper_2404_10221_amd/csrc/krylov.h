@@ -71,13 +71,15 @@ inline int kry_blocks(int64_t n) {
   return (int)b;
 }
 
-// Blocks for an instance of a many-instance handle: at least 4096 entries per
+// Blocks for an instance of a many-instance handle: at least 8192 entries per
 // block.  Every block of a sweep first reduces the previous sweep's partials and
 // forms the projection coefficients; with the single-instance count (one block
 // per 1024 entries) that prologue outweighed the vector work of the small
-// instances, and the batched launches already fill the GPU with many instances.
+// instances, and the batched launches already fill the GPU with many instances
+// (64 instances of 127^2 to 511^2: 4096 entries per block gave 187.5, 8192
+// gave 193, 16384 gave 191 steps/s).
 inline int kry_blocks_many(int64_t n) {
-  int64_t b = (n + 4095) / 4096;
+  int64_t b = (n + 8191) / 8192;
   if (b > RSFDE_KRY_BLOCKS) b = RSFDE_KRY_BLOCKS;
   if (b < 1) b = 1;
   return (int)b;
