@@ -31,6 +31,13 @@ __device__ __forceinline__ double sine_modes(const FieldDev& F, int d, const int
   return acc;
 }
 
+// The separable e families from their per-axis product p (one expression, shared
+// by the generic and the grid-shaped kernels so that both round alike).
+__device__ __forceinline__ double e_separable(const FieldDev& E, double p, double t, const TimeF& tf) {
+  if (E.kind == RSFDE_FIELD_POLY_T) return E.c[0] + E.c[1] * (1.0 + E.c[2] * t) * p;
+  return E.c[0] + E.c[1] * p * tf.cos_t;
+}
+
 __device__ __forceinline__ double e_value(const FieldDev& E, int d, const double* x, const int* jc,
                                           const int* Ncl, double t, const TimeF& tf) {
   switch (E.kind) {
@@ -41,15 +48,11 @@ __device__ __forceinline__ double e_value(const FieldDev& E, int d, const double
       for (int i = 0; i < d; ++i) s += x[i] * x[i];
       return (s + tf.exp_mt) / E.c[0];
     }
-    case RSFDE_FIELD_POLY_T: {
-      double p = 1.0;  // prod_i x_i^c3 (table row AX_E)
+    case RSFDE_FIELD_POLY_T:       // p = prod_i x_i^c3 (table row AX_E)
+    case RSFDE_FIELD_SINPROD_COS: {  // p = prod_i sin(pi x_i)
+      double p = 1.0;
       for (int i = 0; i < d; ++i) p *= E.ax[i][AX_E * Ncl[i] + jc[i]];
-      return E.c[0] + E.c[1] * (1.0 + E.c[2] * t) * p;
-    }
-    case RSFDE_FIELD_SINPROD_COS: {
-      double p = 1.0;  // prod_i sin(pi x_i) (table row AX_E)
-      for (int i = 0; i < d; ++i) p *= E.ax[i][AX_E * Ncl[i] + jc[i]];
-      return E.c[0] + E.c[1] * p * tf.cos_t;
+      return e_separable(E, p, t, tf);
     }
     case RSFDE_FIELD_SINE_FIELD: {
       const double g = sine_modes(E, d, jc, Ncl);
@@ -161,9 +164,50 @@ hipError_t fields_eval_batched(const FieldJob* jobs, const int* start, int n, in
   return hipGetLastError();
 }
 
+// e of the separable families (POLY_T, SINPROD_COS) on a grid-shaped launch: x_1
+// along the block's threads, x_2 and x_3 from the block indices, so no thread
+// splits a flat index; p multiplies the axis factors in the order the generic
+// kernel does.
+template <int D>
+__global__ void __launch_bounds__(256)
+k_e_separable(const FieldDev E, const GridDev g, double t, const TimeF tf, double* __restrict__ out) {
+  const int off = g.closure ? 0 : 1;
+  const int n0 = g.closure ? g.N[0] + 2 : g.N[0];
+  const int j0 = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (j0 >= n0) return;
+  double p = 1.0;
+  p *= E.ax[0][AX_E * (g.N[0] + 2) + j0 + off];
+  int64_t row = 0;
+  if constexpr (D >= 2) {
+    const int j1 = (int)blockIdx.y;
+    p *= E.ax[1][AX_E * (g.N[1] + 2) + j1 + off];
+    row = j1;
+  }
+  if constexpr (D == 3) {
+    const int j2 = (int)blockIdx.z;
+    const int n1 = g.closure ? g.N[1] + 2 : g.N[1];
+    p *= E.ax[2][AX_E * (g.N[2] + 2) + j2 + off];
+    row += (int64_t)j2 * n1;
+  }
+  out[row * n0 + j0] = e_separable(E, p, t, tf);
+}
+
 hipError_t fields_eval(const FieldDev& e, const FieldDev& f, int which, const GridDev& g, double t,
                        double* out, hipStream_t s) {
   if (g.size == 0) return hipSuccess;
+  if (which == RSFDE_WHICH_E && (e.kind == RSFDE_FIELD_POLY_T || e.kind == RSFDE_FIELD_SINPROD_COS)) {
+    const int c = g.closure ? 2 : 0;
+    const unsigned n0 = (unsigned)(g.N[0] + c);
+    const unsigned n1 = g.d >= 2 ? (unsigned)(g.N[1] + c) : 1u;
+    const unsigned n2 = g.d >= 3 ? (unsigned)(g.N[2] + c) : 1u;
+    if (n1 <= 65535u && n2 <= 65535u) {
+      const dim3 grid((n0 + 255) / 256, n1, n2);
+      if (g.d == 1) hipLaunchKernelGGL(k_e_separable<1>, grid, dim3(256), 0, s, e, g, t, time_factors(t), out);
+      else if (g.d == 2) hipLaunchKernelGGL(k_e_separable<2>, grid, dim3(256), 0, s, e, g, t, time_factors(t), out);
+      else hipLaunchKernelGGL(k_e_separable<3>, grid, dim3(256), 0, s, e, g, t, time_factors(t), out);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL(k_fields_eval, dim3((unsigned)((g.size + 255) / 256)), dim3(256), 0, s, e, f,
                      which, g, t, time_factors(t), out);
   return hipGetLastError();
