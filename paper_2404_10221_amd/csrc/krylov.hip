@@ -324,6 +324,21 @@ __device__ __forceinline__ void sweepB_body(const KryArgs& a, int bid, int nblk)
   __shared__ double tb[KM], db[KM];
   __shared__ double cfq[KM], cfu[KM];
   __shared__ double invr_s;
+  // The thread's first entry pair of w and of the first column chunk is loaded
+  // before the prologue (reduction of sweep A's partials, coefficients), so that
+  // its memory latency overlaps the prologue instead of following it.
+  double* __restrict__ w = a.w;
+  double* __restrict__ V = const_cast<double*>(a.V);
+  const int64_t stride = (int64_t)nblk * NT;
+  const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
+  double2* __restrict__ w2 = (double2*)w;
+  double2* __restrict__ V2 = (double2*)V;
+  const int64_t i0 = (int64_t)bid * NT + threadIdx.x;
+  const int64_t ip = i0 < n2 ? i0 : 0;  // (a valid address; unused past the end)
+  const double2 w_pre = w2[ip];
+  double2 v_pre[CH];
+  ld_cols<CH>(v_pre, (const double2*)V2, ld2, ip, 0, nv);
+  asm volatile("" ::: "memory");  // (keeps those loads ahead of the prologue's)
   reduce_partials<KM, NT>(a.pa, nblk, nv, tb);
   if (j >= 1)
     reduce_partials<KM, NT>(split ? a.pb : a.pa + (int64_t)nv * RSFDE_PVS, nblk, nv, db);
@@ -359,20 +374,19 @@ __device__ __forceinline__ void sweepB_body(const KryArgs& a, int bid, int nblk)
   __syncthreads();
   const double ir = invr_s;
   double acc[1] = {0.0};
-  double* __restrict__ w = a.w;
-  double* __restrict__ V = const_cast<double*>(a.V);
-  const int64_t stride = (int64_t)nblk * NT;
-  const int64_t n2 = a.n >> 1, ld2 = a.ldv >> 1;
-  double2* __restrict__ w2 = (double2*)w;
-  double2* __restrict__ V2 = (double2*)V;
-  for (int64_t i = (int64_t)bid * NT + threadIdx.x; i < n2; i += stride) {
-    const double2 wi = w2[i];
+  // one entry pair: column chunk 0 comes in v0, the later chunks are loaded here
+  auto row = [&](const int64_t i, const double2 wi, const double2 (&v0)[CH]) {
     double2 qn = {0.0, 0.0}, u = {wi.x * ir, wi.y * ir};
 #pragma unroll
     for (int kb = 0; kb < KM; kb += CH)
       if (kb < nv) {
         double2 v[CH];
-        ld_cols<CH>(v, (const double2*)V2, ld2, i, kb, nv);
+        if (kb == 0) {
+#pragma unroll
+          for (int cc = 0; cc < CH; ++cc) v[cc] = v0[cc];
+        } else {
+          ld_cols<CH>(v, (const double2*)V2, ld2, i, kb, nv);
+        }
 #pragma unroll
         for (int cc = 0; cc < CH; ++cc) {
           const int k = kb + cc;
@@ -391,6 +405,13 @@ __device__ __forceinline__ void sweepB_body(const KryArgs& a, int bid, int nblk)
     if (j >= 1) V2[(int64_t)j * ld2 + i] = qn;
     w2[i] = u;
     acc[0] += u.x * u.x + u.y * u.y;
+  };
+  if (i0 < n2) row(i0, w_pre, v_pre);
+  for (int64_t i = i0 + stride; i < n2; i += stride) {
+    const double2 wi = w2[i];
+    double2 v0[CH];
+    ld_cols<CH>(v0, (const double2*)V2, ld2, i, 0, nv);
+    row(i, wi, v0);
   }
   if ((a.n & 1) && bid == 0 && threadIdx.x == 0) {
     const int64_t i = a.n - 1;
