@@ -104,14 +104,18 @@ __device__ __forceinline__ void set_comp(cpx<R>& z, int c, R v) {
 
 // Pitch (in elements) of the F sequences of a workgroup.  In a strided tile the
 // lanes of a wavefront cover 2F pencils at consecutive positions, i.e. the same
-// positions of F sequences; starting consecutive sequences 256/F bytes apart
-// modulo 256 gives those F x (positions) accesses one bank each.
+// positions of F sequences, as 8-byte component accesses.  Consecutive sequences
+// start W/F bytes apart modulo W, so that the F sequences x two components x the
+// consecutive positions of a lane group fall on distinct banks: W = 128 bytes for
+// the plain FP64 layout (the LDS serves a wave-wide access in 128-byte groups of
+// 32 banks), W = 256 for the padded FP32 one.
 template <typename R, int L, int F>
 struct LdsPitch {
   static constexpr int S = LdsSeq<R, L>::size;
   static constexpr int EB = (int)sizeof(cpx<R>);
+  static constexpr int W = LdsSeq<R, L>::PAD ? 256 : 128;
   static constexpr int M = 256 / EB;  // elements per 256 bytes
-  static constexpr int want = F == 1 ? 0 : ((256 / F) / EB > 1 ? (256 / F) / EB : 1);
+  static constexpr int want = F == 1 ? 0 : ((W / F) / EB > 1 ? (W / F) / EB : 1);
   static constexpr int value = S + ((want - S % M) % M + M) % M;
 };
 
