@@ -118,3 +118,29 @@ def test_params_from_paper_example():
     p = R.params_from_instance(paper_example(2, (1.1, 1.3), 16, 4096))
     assert p.d == 2 and p.n[0] == 15 and abs(p.dt - 1 / 4096) < 1e-18
     assert R.rsfde_workspace_size([p]) > 0
+
+
+def test_shipped_tune_cache_is_well_formed():
+    """tune_cache.txt beside the library: comment lines, then one
+    'arch d<d> ax<a> fp<p> cls<c> L<len>=<variant>' line per autotuned pass, each
+    key once, variants 0..5, and only transform lengths the library carries."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(R.__file__), "tune_cache.txt")
+    assert os.path.exists(path)
+    seen = set()
+    pat = re.compile(r"^(gfx\S+) d([123]) ax([012]) fp([01]) cls([01]) L(\d+)=([0-5])$")
+    lengths = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048,
+               3072, 4096}
+    for line in open(path).read().splitlines():
+        if not line or line.startswith("#"):
+            assert "=" not in line  # the loader would read it as an entry
+            continue
+        m = pat.match(line)
+        assert m, line
+        key = line.rsplit("=", 1)[0]
+        assert key not in seen, key
+        seen.add(key)
+        d, ax = int(m.group(2)), int(m.group(3))
+        assert ax < d and int(m.group(6)) in lengths, line
+    assert len(seen) >= 30
