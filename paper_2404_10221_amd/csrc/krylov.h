@@ -125,7 +125,7 @@ __device__ __forceinline__ double gm_lane(double x, int i) {
 // sits between the loads, so none of them waits for another (or for the tile
 // loads issued after them).
 struct GmIn {
-  double pv[RSFDE_PVS / 64];  // sweep-3 partials lane + 64 q
+  double pv[RSFDE_PVS / 64];  // sweep-B norm partials lane + 64 q
   double h, h2, cs, sn;
   double gam, thr, vsc;
   int fl, kfin;
@@ -265,9 +265,9 @@ struct KryArgs {
   int64_t n;
   double* w;          // working vector (column j+1 of V)
   GmresState* st;
-  double* pa;         // sweep-1 partials
-  double* pb;         // sweep-2 partials
-  double* pc;         // sweep-3 partials
+  double* pa;         // sweep-A partials (dot products of the basis with w and with u_j)
+  double* pb;         // sweep-D partials (sums with column j, when sweep A splits)
+  double* pc;         // sweep-B partials (||u_{j+1}||^2)
   int j;              // Arnoldi index (w = P^{-1} A v_j)
   int m;              // restart length
   int nb;             // blocks of the sweeps (kry_blocks or kry_blocks_many)

@@ -167,9 +167,9 @@ __device__ __forceinline__ void ld_cols(T (&v)[C], const T* __restrict__ V, int6
   }
 }
 
-// ---- CGS2 sweep 1: partials of Vbar^T w ---------------------------------------------------
+// ---- partials of Vbar^T w (the body of sweep D) -----------------------------------------
 template <int KM>
-__device__ __forceinline__ void sweep1_body(const KryArgs& a, int bid, int nblk) {
+__device__ __forceinline__ void sweepD_body(const KryArgs& a, int bid, int nblk) {
   constexpr int NT = SweepNT<1, KM>::value;
   constexpr int CH = KM < 8 ? KM : 8;
   if (a.st->FL[a.j] != GM_RUNNING) return;
@@ -213,10 +213,6 @@ __device__ __forceinline__ void sweep1_body(const KryArgs& a, int bid, int nblk)
   if ((int)threadIdx.x < nv) a.pa[threadIdx.x * RSFDE_PVS + bid] = res[threadIdx.x];
 }
 
-template <int KM>
-__global__ void __launch_bounds__((SweepNT<1, KM>::value)) k_sweep1(const KryArgs a) {
-  sweep1_body<KM>(a, blockIdx.x, gridDim.x);
-}
 
 // ---- Arnoldi step j: CGS2 with the second projection delayed by one step ---------------
 //
@@ -236,7 +232,7 @@ __global__ void __launch_bounds__((SweepNT<1, KM>::value)) k_sweep1(const KryArg
 // second-projection coefficients of plain CGS2.  Two sweeps per Arnoldi step
 // instead of three, and 2j + 6 vector reads and writes instead of 3j + 7.
 // Sweep A holds 2(j+1) sums; past 64 (j >= 32) the sums Vbar_k . Vbar_j come from
-// a third sweep (sweep 1 on column j) into the second partial buffer.
+// a third sweep (sweep D, the same sums on column j) into the second partial buffer.
 
 // Sweep A: partials of Vbar_k . w (values 0..j) and, for j >= 1, Vbar_k . Vbar_j
 // (values j+1 .. 2j+1).
@@ -301,13 +297,13 @@ __global__ void __launch_bounds__((SweepNT<1, KM>::value)) k_sweepA(const KryArg
   sweepA_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
-// Sweep 1 on column j: partials of Vbar_k . Vbar_j (k <= j) into pb (steps j >= 32).
+// Sweep D: partials of Vbar_k . Vbar_j (k <= j) into pb, when sweep A cannot hold both sets.
 template <int KM>
 __global__ void __launch_bounds__((SweepNT<1, KM>::value)) k_sweepD(const KryArgs a) {
   KryArgs d = a;
   d.w = const_cast<double*>(a.V) + (int64_t)a.j * a.ldv;
   d.pa = a.pb;
-  sweep1_body<KM>(d, blockIdx.x, gridDim.x);
+  sweepD_body<KM>(d, blockIdx.x, gridDim.x);
 }
 
 // Sweep B.  `split`: the sums Vbar_k . Vbar_j are in pb (values 0..j) instead of pa
@@ -584,7 +580,7 @@ __global__ void __launch_bounds__((SweepNT<W, KM>::value)) k_sweep_b(const KLaun
     KryArgs dd = a;  // sums of the columns with column j, into pb (j >= 32)
     dd.w = const_cast<double*>(a.V) + (int64_t)a.j * a.ldv;
     dd.pa = a.pb;
-    sweep1_body<KM>(dd, bid, d.nb);
+    sweepD_body<KM>(dd, bid, d.nb);
   } else {
     sweepB_body<KM>(a, bid, d.nb);
   }
