@@ -199,6 +199,17 @@ int rsfde_step(rsfde_handle h, double t_m, const double* const* e_half,
 int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx,
                 double* const* u, rsfde_stats* stats);
 
+/* Steps m0 .. m0+M-1 (t_m = m dt, m0 >= 0) of the same time loop as rsfde_solve,
+ * which is the case m0 = 0: u[i] holds u^{(m0)} on entry and u^{(m0+M)} on exit.
+ * The loop runs in the library, so a long run split over several calls
+ * continues the same time levels without a host round trip per step.  An
+ * instance whose ebar is not known yet is pre-scanned over this call's M
+ * midpoints only; a run split over several calls should set ebar for all of its
+ * steps first (rsfde_prescan_ebar or rsfde_set_ebar).  Errors as rsfde_solve,
+ * and RSFDE_E_INVALID_ARG for m0 < 0. */
+int rsfde_solve_range(rsfde_handle h, int m0, int M, rsfde_sample_fn sample, void* ctx,
+                      double* const* u, rsfde_stats* stats);
+
 /* Release the host state of a handle (not the caller's workspace). */
 int rsfde_destroy(rsfde_handle h);
 

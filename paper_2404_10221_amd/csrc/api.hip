@@ -2060,7 +2060,12 @@ static int builtin_sample(rsfde_ctx* h, Inst& I, double t, bool need_f) {
 
 int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx, double* const* u,
                 rsfde_stats* stats) {
-  if (!h || M < 0 || !u) return RSFDE_E_INVALID_ARG;
+  return rsfde_solve_range(h, 0, M, sample, ctx, u, stats);
+}
+
+int rsfde_solve_range(rsfde_handle h, int m0, int M, rsfde_sample_fn sample, void* ctx,
+                      double* const* u, rsfde_stats* stats) {
+  if (!h || m0 < 0 || M < 0 || !u) return RSFDE_E_INVALID_ARG;
   for (int i = 0; i < h->count; ++i) {
     if (!u[i]) return RSFDE_E_INVALID_ARG;
     if (!sample && !h->inst[i].fe.set) return RSFDE_E_STATE;
@@ -2074,7 +2079,7 @@ int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx, double
     const bool tindep = !sample && !I.fe.spec.time_dependent;
     const int scans = tindep ? std::min(M, 1) : M;
     for (int m = 0; m < scans; ++m) {
-      const double th = (m + 0.5) * I.p.dt;
+      const double th = (m0 + m + 0.5) * I.p.dt;
       if (sample) {
         if (sample(ctx, i, th, I.e, I.f, (void*)h->stream) != 0) return RSFDE_E_INVALID_ARG;
       } else {
@@ -2095,7 +2100,7 @@ int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx, double
     if (h->batched) {
       for (int i = 0; i < h->count; ++i) {
         Inst& I = h->inst[i];
-        const double th = (m + 0.5) * I.p.dt;
+        const double th = (m0 + m + 0.5) * I.p.dt;
         if (sample) {
           if (sample(ctx, i, th, I.e, I.f, (void*)h->stream) != 0) return RSFDE_E_INVALID_ARG;
         } else {
@@ -2122,7 +2127,7 @@ int rsfde_solve(rsfde_handle h, int M, rsfde_sample_fn sample, void* ctx, double
     }
     for (int i = 0; i < h->count; ++i) {
       Inst& I = h->inst[i];
-      const double th = (m + 0.5) * I.p.dt;
+      const double th = (m0 + m + 0.5) * I.p.dt;
       if (sample) {
         if (sample(ctx, i, th, I.e, I.f, (void*)h->stream) != 0) return RSFDE_E_INVALID_ARG;
       } else {

@@ -41,7 +41,7 @@ EXPORTED = (
     "rsfde_eval_field_batch", "rsfde_set_graph", "rsfde_apply_A",
     "rsfde_apply_prec", "rsfde_apply_prec_form", "rsfde_compute_F", "rsfde_rhs", "rsfde_get_tables", "rsfde_set_timing",
     "rsfde_get_timing", "rsfde_prescan_ebar", "rsfde_get_pass_shape", "rsfde_set_true_residual",
-    "rsfde_apply_prec_noalloc", "rsfde_get_pass_plan",
+    "rsfde_apply_prec_noalloc", "rsfde_get_pass_plan", "rsfde_solve_range",
 )
 
 K_CLASSES = ("mv_first", "mv_mid", "mv_last", "dst", "dsd", "dots", "orth_dots", "orth_norm", "update")
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
     lib.rsfde_set_ebar.argtypes = [P, I, D, D]
     lib.rsfde_step.argtypes = [P, D, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(rsfde_stats)]
     lib.rsfde_solve.argtypes = [P, I, SAMPLE_FN, P, C.POINTER(P), C.POINTER(rsfde_stats)]
+    lib.rsfde_solve_range.argtypes = [P, I, I, SAMPLE_FN, P, C.POINTER(P), C.POINTER(rsfde_stats)]
     lib.rsfde_destroy.argtypes = [P]
     lib.rsfde_strerror.argtypes = [I]
     lib.rsfde_strerror.restype = C.c_char_p
@@ -231,6 +232,14 @@ def rsfde_solve(h, M: int, u: Sequence, sample=None, ctx=None) -> tuple:
     st = (rsfde_stats * len(u))()
     fn = SAMPLE_FN(0) if sample is None else SAMPLE_FN(sample)
     s = _check(load_library().rsfde_solve(h, int(M), fn, ctx, _ptr_array(u), st), "rsfde_solve")
+    return s, [x.as_dict() for x in st]
+
+
+def rsfde_solve_range(h, m0: int, M: int, u: Sequence, sample=None, ctx=None) -> tuple:
+    st = (rsfde_stats * len(u))()
+    fn = SAMPLE_FN(0) if sample is None else SAMPLE_FN(sample)
+    s = _check(load_library().rsfde_solve_range(h, int(m0), int(M), fn, ctx, _ptr_array(u), st),
+               "rsfde_solve_range")
     return s, [x.as_dict() for x in st]
 
 
