@@ -340,8 +340,9 @@ def main():
     ap.add_argument("--cpu-instances", type=int, default=4,
                     help="instances of a many-instance workload the oracle baseline samples")
     ap.add_argument("--workload", default="C2", choices=("C1", "C2", "C3", "C4", "C5"))
-    ap.add_argument("--timing-every", type=int, default=4,
-                    help="time one launch in this many of the dominant kernel class")
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="time one launch in this many of the dominant kernel class (a stamped "
+                         "dispatch waits about 5 us longer to start)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
