@@ -341,6 +341,7 @@ struct rsfde_ctx {
   bool true_res = false;                 // rsfde_set_true_residual
   hipStream_t stream = nullptr;
   GmresSummary* pinned = nullptr;
+  hipEvent_t sync_ev = nullptr;          // stream_wait's event (created on first use)
   unsigned tmask = 0;
   int tevery = 1;
   long long tseen[RSFDE_K_NCLASS] = {0};
@@ -912,9 +913,30 @@ static int eval_field(rsfde_ctx* h, Inst& I, int which, double t, double* out) {
 // ---------------------------------------------------------------------------
 // one step of one instance
 // ---------------------------------------------------------------------------
+// Wait for the stream's work enqueued so far by spinning on an event query.  The
+// read of a chunk's status is on the critical path (the GPU idles until the
+// host launches what follows), and a blocking synchronisation adds the host
+// thread's wake-up latency to that idle time.
+static hipError_t stream_wait(rsfde_ctx* h) {
+  static const bool blocking = [] {
+    const char* e = getenv("RSFDE_BLOCKING_SYNC");
+    return e && atoi(e) != 0;
+  }();
+  if (blocking) return hipStreamSynchronize(h->stream);
+  if (!h->sync_ev) {
+    const hipError_t e = hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipEventRecord(h->sync_ev, h->stream);
+  if (e != hipSuccess) return e;
+  while ((e = hipEventQuery(h->sync_ev)) == hipErrorNotReady) {
+  }
+  return e;
+}
+
 static int read_summary(rsfde_ctx* h, const Inst& I, GmresSummary* out) {
   CK(hipMemcpyAsync(h->pinned, &I.st->sum, sizeof(GmresSummary), hipMemcpyDeviceToHost, h->stream));
-  CK(hipStreamSynchronize(h->stream));
+  CK(stream_wait(h));
   *out = *h->pinned;
   if (!h->pending.empty()) {
     if (out->flag != GM_RUNNING) mark_speculative(h, out->k);
@@ -1441,7 +1463,7 @@ static int read_summaries(rsfde_ctx* h, const KPlan& kp) {
   CK(kry_gather_summaries(kp.desc, kp.ninst, h->dsum, h->stream));
   CK(hipMemcpyAsync(h->psum, h->dsum, kp.ninst * sizeof(GmresSummary), hipMemcpyDeviceToHost,
                     h->stream));
-  CK(hipStreamSynchronize(h->stream));
+  CK(stream_wait(h));
   if (!h->pending.empty()) {
     // a batched launch of step j did work while some instance's cycle had not
     // ended before j (instances that ended earlier exit inside it)
@@ -2161,6 +2183,7 @@ int rsfde_destroy(rsfde_handle h) {
     (void)hipEventDestroy(tp.b);
   }
   for (auto ev : h->ev_free) (void)hipEventDestroy(ev);
+  if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
   for (auto& I : h->inst) graphs_clear(I.gexec);
   graphs_clear(h->bgexec);
   if (h->cap) (void)hipStreamDestroy(h->cap);
