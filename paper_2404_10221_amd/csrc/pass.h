@@ -80,11 +80,16 @@ __device__ __forceinline__ R ld_any(const void* p, int64_t i, bool is64) {
   }
 }
 
-// NT: a non-temporal store (the nt cache policy).  The contiguous-axis passes
-// store their pencils so.  Measured per step: 3-D 255^3 2 % faster (the passes'
-// own stores get slower, the strided passes and the sweeps that follow them
-// faster), 64 instances of 2-D 1.4 %, 1-D 511, 2-D 1023^2 and 3-D 511^3 within
-// noise.  Non-temporal stores in the strided passes were much slower (3-D 255^3
+// NT: a non-temporal store (the nt cache policy).  The contiguous-axis passes of
+// transform lengths up to 1024 store their pencils so (a compile-time choice: a
+// branch between the two store forms is merged by the compiler, which drops the
+// hint).  Measured per step with non-temporal stores in every contiguous pass:
+// 3-D 255^3 (L = 512) 2 % faster (the passes' own stores get slower, the strided
+// passes and the sweeps that follow them faster), 64 instances of 2-D (L = 256 ..
+// 1024) 1.4 %, 3-D 511^3 and 1-D 511 (L = 1024) within noise; on 2-D 1023^2
+// (L = 2048) the step rate did not move but the strided pass reading the
+// non-temporal output slowed from 21 to 23 us, so L = 2048 and up keep plain
+// stores.  Non-temporal stores in the strided passes were much slower (3-D 255^3
 // sine-transform pass 78 -> 125 us), and in the Arnoldi sweeps made no difference.
 template <typename R, bool NT = false>
 __device__ __forceinline__ void st_any(void* p, int64_t i, R v, bool is64) {
@@ -199,6 +204,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
   const int N = a.N;
   const bool in64 = (a.flags & FL_IN64) != 0;
   const bool out64 = (a.flags & FL_OUT64) != 0;
+  constexpr bool NT_ST = !STRIDED && plan_len(L) <= 1024;  // (see st_any)
 
   // ---- tile geometry.  Blocks are dispatched round-robin over the 8 XCDs
   // (each with its own L2); for strided passes every XCD takes a contiguous run
@@ -448,8 +454,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
     for (int i = 0; i < NE; ++i) {
       const int k = t + i * T;
       if (k >= 1) {
-        if (v0) st_any<R, true>(a.out_a, b0 + k, -c[i].y, out64);
-        if (v1) st_any<R, true>(a.out_a, b1 + k, c[i].x, out64);
+        if (v0) st_any<R, NT_ST>(a.out_a, b0 + k, -c[i].y, out64);
+        if (v1) st_any<R, NT_ST>(a.out_a, b1 + k, c[i].x, out64);
       }
     }
     return;
@@ -547,8 +553,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           cpx<R> ba = buf[N + 1 + p] * bd + (buf[N + p] + buf[N + 2 + p]) * bo;
           ra[i] = ba;
           if (store_c) {
-            if (v0) st_any<R, true>(a.out_c, b0 + p, bc.x, false);
-            if (v1) st_any<R, true>(a.out_c, b1 + p, bc.y, false);
+            if (v0) st_any<R, NT_ST>(a.out_c, b0 + p, bc.x, false);
+            if (v1) st_any<R, NT_ST>(a.out_c, b1 + p, bc.y, false);
           }
         }
       }
@@ -629,8 +635,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
           if (want_dst) {
             ra[i] = w;
           } else {
-            if (v0) st_any<R, true>(a.out_a, b0 + p, w.x, out64 && last);
-            if (v1) st_any<R, true>(a.out_a, b1 + p, w.y, out64 && last);
+            if (v0) st_any<R, NT_ST>(a.out_a, b0 + p, w.x, out64 && last);
+            if (v1) st_any<R, NT_ST>(a.out_a, b1 + p, w.y, out64 && last);
           }
         }
       }
@@ -772,8 +778,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
       const int p = t + i * T;
       if (p < N) {
         const cpx<R> Z = buf[p + 1];
-        if (v0) st_any<R, true>(a.out_a, b0 + p, -Z.y, out64);
-        if (v1) st_any<R, true>(a.out_a, b1 + p, Z.x, out64);
+        if (v0) st_any<R, NT_ST>(a.out_a, b0 + p, -Z.y, out64);
+        if (v1) st_any<R, NT_ST>(a.out_a, b1 + p, Z.x, out64);
       }
     }
   } else {
