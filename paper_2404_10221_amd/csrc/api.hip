@@ -305,6 +305,7 @@ struct RecPass {
   PassArgs a;
   bool fp32;
   int inst;
+  bool stop_pend;  // runs before the step's resolve: stops on the pending step's status
 };
 
 struct rsfde_ctx {
@@ -338,6 +339,7 @@ struct rsfde_ctx {
   const int* fjob_start = nullptr;
   std::vector<RecPass>* rec = nullptr;  // chain recording instead of launching
   int rec_inst = -1;
+  bool rec_stop_pend = false;           // passes recorded now carry RecPass::stop_pend
   bool true_res = false;                 // rsfde_set_true_residual
   hipStream_t stream = nullptr;
   GmresSummary* pinned = nullptr;
@@ -561,7 +563,7 @@ static int op_class(int op) {
 static int run_pass(rsfde_ctx* h, const Inst& I, const PassArgs& a, bool fp32) {
   const int L = I.ax[a.axis].L;
   if (h->rec) {
-    h->rec->push_back(RecPass{a, fp32, h->rec_inst});
+    h->rec->push_back(RecPass{a, fp32, h->rec_inst, h->rec_stop_pend});
     return RSFDE_OK;
   }
   if (a.ntiles <= 0) return RSFDE_OK;
@@ -598,15 +600,16 @@ static int flush_timing(rsfde_ctx* h) {
 
 // Transform, diagonal scaling (PM_*), transform for an FP64 r: (BP)^{-1} r, or
 // a factor of the two-sided form.  Temporaries T[0], T[1], T[2], T[3] in turn
-// (d = 3); out may be T[2], r may be T[3].
+// (d = 3); out may be T[2], r may be T[3].  accum: the result is added to out.
 static int run_prec(rsfde_ctx* h, const Inst& I, bool fp32, const double* r, double* out,
                     int pmode = PM_BP_INV, const int* stop_fl = nullptr,
-                    void* const* temps = nullptr) {
+                    void* const* temps = nullptr, bool accum = false) {
   const int d = I.d;
   void* const* T = temps ? temps : I.tmp;
+  const int acc = accum ? FL_ACCUM : 0;
   if (d == 1) {
     PassArgs t = mk_pass(I, 0, OP_DSD, fp32);
-    t.flags = FL_IN64 | FL_OUT64;
+    t.flags = FL_IN64 | FL_OUT64 | acc;
     t.in_c = r;
     t.out_a = out;
     t.pmode = pmode;
@@ -639,7 +642,7 @@ static int run_prec(rsfde_ctx* h, const Inst& I, bool fp32, const double* r, dou
     t.in_c = T[cur];
     const bool last = ax == d - 1;
     const int o = (cur + 1) & 3;
-    t.flags = last ? FL_OUT64 : 0;
+    t.flags = last ? FL_OUT64 | acc : 0;
     t.out_a = last ? (void*)out : T[o];
     t.stop_fl = stop_fl;
     CKS(run_pass(h, I, t, fp32));
@@ -756,7 +759,10 @@ static int run_chain(rsfde_ctx* h, const Inst& I, int kind, bool fp32, const dou
   if (two && kind == CH_OPER) {
     // runs before the step's resolve: exit on the status before the pending step
     const int* pre_stop = gm ? &I.st->FL[gm->pend >= 0 ? gm->pend : gm->j] : stop_fl;
-    CKS(run_prec(h, I, fp32, x, (double*)I.tmp[2], PM_PH, pre_stop));
+    h->rec_stop_pend = gm != nullptr;
+    const int pre_status = run_prec(h, I, fp32, x, (double*)I.tmp[2], PM_PH, pre_stop);
+    h->rec_stop_pend = false;
+    CKS(pre_status);
     x = (const double*)I.tmp[2];
   }
   const double sgn = kind == CH_RHS ? -1.0 : 1.0;
@@ -1062,20 +1068,17 @@ static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* 
     gu.j = jend - 1;
     gu.pend = jend - 1;
     gu.m = m;
-    // two-sided form: the update V y lands in T[3] (zeroed first) and
-    // u += P^{-1/2} (V y) once the cycle has ended
+    // two-sided form: the update V y is written to T[3] and u += P^{-1/2} (V y)
+    // once the cycle has ended (the last pass of the factor adds into u)
     const bool two = I.p.method == RSFDE_TPGM;
     double* xu = two ? (double*)I.tmp[3] : x;
-    if (two) CK(fill_f64(xu, I.n, 0.0, h->stream));
     CKS(timed_launch(h, RSFDE_K_UPDATE, 0.0, [&](hipEvent_t ea, hipEvent_t eb) {
-      return kry_update(I.V, I.ldv, I.n, xu, gu, h->stream, ea, eb);
+      return kry_update(I.V, I.ldv, I.n, xu, gu, h->stream, ea, eb, two ? 1 : 0);
     }));
     CKS(read_summary(h, I, S));
     if (S->flag != GM_RUNNING) {
-      if (two && S->flag != GM_NONFINITE) {
-        CKS(run_prec(h, I, fp32, xu, (double*)I.tmp[2], PM_PH));
-        CK(axpy_f64((const double*)I.tmp[2], x, I.n, h->stream));
-      }
+      if (two && S->flag != GM_NONFINITE && S->k > 0)
+        CKS(run_prec(h, I, fp32, xu, x, PM_PH, nullptr, nullptr, true));
       return RSFDE_OK;
     }
     j = jend;
@@ -1223,18 +1226,20 @@ static bool batchable(const rsfde_ctx* h) {
   // addresses exist in every instance)
   for (const Inst& I : h->inst)
     if (I.d != h->inst[0].d || I.p.precision != h->inst[0].p.precision ||
-        I.p.restart != h->inst[0].p.restart || I.p.method != RSFDE_OPGM)
+        I.p.restart != h->inst[0].p.restart || I.p.method != h->inst[0].p.method ||
+        I.p.method == RSFDE_SPGM)
       return false;
   return true;
 }
 
 // Descriptor buffer capacity of one plan region for `count` instances: three
-// chains of at most 7 pass positions with a descriptor and a block-start entry
-// per instance (64-byte aligned per group), the Krylov descriptors with two
-// start arrays, and the source-operator jobs.
+// chains of at most 12 pass positions (the two-sided operator chain in 3-D: its
+// right factor, 5, and the operator with the left factor, 7) with a descriptor
+// and a block-start entry per instance (64-byte aligned per group), the Krylov
+// descriptors with two start arrays, and the source-operator jobs.
 static size_t plan_capacity(int count) {
   const size_t per_pos = (size_t)count * (sizeof(BPass) + 3 * 64 + 8) + 64;
-  return 3 * 7 * per_pos + (size_t)count * (sizeof(KBatch) + sizeof(FJob) + 32) + 8 * 64 + 4096;
+  return 3 * 12 * per_pos + (size_t)count * (sizeof(KBatch) + sizeof(FJob) + 32) + 8 * 64 + 4096;
 }
 static size_t fjob_capacity(int count) {
   return (size_t)count * (sizeof(FieldJob) + 8) + 4 * 64 + 1024;
@@ -1314,7 +1319,8 @@ static int plan_chain(rsfde_ctx* h, int r, const std::vector<int>& S, RecFn rec_
           if (rp.a.in_c == (const void*)I.V) b.patch |= BP_IN_J;
           if (rp.a.out_a == (void*)(I.V + I.ldv)) b.patch |= BP_OUT_J;
           if (rp.a.use_gm) b.patch |= BP_GM;
-          if (rp.a.stop_fl == &I.st->FL[0]) b.patch |= BP_STOP;
+          if (rp.stop_pend) b.patch |= BP_STOP_PEND;
+          else if (rp.a.stop_fl == &I.st->FL[0]) b.patch |= BP_STOP;
         }
         desc.push_back(b);
         const int64_t nb = (rp.a.nlaunch + 7) / 8 * 8;  // 8-aligned: XCD order kept per instance
@@ -1370,7 +1376,10 @@ static int plan_krylov(rsfde_ctx* h, int r, const std::vector<int>& S, double* c
     d.k.pc = I.pk[2];
     d.k.j = 0;
     d.k.m = I.p.restart;
-    d.x = u[i];
+    // two-sided form: the update writes V y to T[3]; the host adds P^{-1/2} of it to u
+    const bool two = I.p.method == RSFDE_TPGM;
+    d.x = two ? (double*)I.tmp[3] : u[i];
+    d.overwrite = two ? 1 : 0;
     d.partial = I.partial;
     d.rtol = I.p.precision == RSFDE_MIXED ? outer_tol(I.p) : I.p.rtol;
     d.inner_rtol = inner_tol(I.p);
@@ -1635,6 +1644,24 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
     std::vector<GmresSummary> fin(C);
     memset(fin.data(), 0, sizeof(GmresSummary) * C);
     CKS(run_cycle_batched(h, go, mixed, *bp, fin));
+    if (h->inst[0].p.method == RSFDE_TPGM) {
+      // u += P^{-1/2} (V y) for the instances whose cycle ended with an update: one
+      // batched chain of the right factor whose last pass adds into u (plan region 1
+      // is free when the cycle ran the full-set plan; else appended after its plan)
+      std::vector<int> corr;
+      for (int i : go)
+        if (fin[i].flag != GM_NONFINITE && fin[i].k > 0) corr.push_back(i);
+      if (!corr.empty()) {
+        if (bp == &bp0) h->rg[1].fill = 0;
+        BChain cc;
+        CKS(plan_chain(h, 1, corr, [&](int i) {
+          Inst& I = h->inst[i];
+          return run_prec(h, I, false, (const double*)I.tmp[3], u[i], PM_PH, nullptr, nullptr, true);
+        }, false, cc));
+        CK(bupload(h, 1));
+        CKS(launch_chain_batched(h, cc, 0, -1));
+      }
+    }
     std::vector<int> next;
     for (int i : go) {
       Inst& I = h->inst[i];

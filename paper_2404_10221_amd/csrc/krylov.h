@@ -291,7 +291,7 @@ struct KBatch {
   int nb;              // blocks of this instance's sweeps and norm (KryArgs::nb)
   int nbu;             // blocks of this instance's update (upd_blocks(n))
   int mixed;
-  int pad;
+  int overwrite;       // the update writes x = V y instead of adding it (two-sided form)
 };
 struct KLaunch {
   const KBatch* desc;  // slot order
@@ -307,8 +307,10 @@ hipError_t kry_cycle_init(double* v0, int64_t n, int nb, GmresState* st, double*
 // ea/eb: when non-null, HIP events stamped at the dispatch's start and end
 hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea = nullptr,
                      hipEvent_t eb = nullptr);  // which = 1, 2, 3
+// x += V y once the cycle has finished (x = V y when overwrite is set)
 hipError_t kry_update(const double* V, int64_t ldv, int64_t n, double* x, const GmRes& g,
-                      hipStream_t s, hipEvent_t ea = nullptr, hipEvent_t eb = nullptr);
+                      hipStream_t s, hipEvent_t ea = nullptr, hipEvent_t eb = nullptr,
+                      int overwrite = 0);
 hipError_t kry_state_reset(GmresState* st, hipStream_t s);
 // batched forms: `nblocks` = start[ninst]; sweeps and norms use KBatch::nb blocks
 // per instance, the update KBatch::nbu, the cycle-start finish one block per instance

@@ -432,9 +432,10 @@ __global__ void __launch_bounds__((SweepNT<2, KM>::value)) k_sweepB(const KryArg
   sweepB_body<KM>(a, blockIdx.x, gridDim.x);
 }
 
-// ---- resolve the last launched step; x += V y when the cycle has finished ----------------
+// ---- resolve the last launched step; x += V y (or x = V y) when the cycle has finished -------
 __device__ __forceinline__ void update_body(const double* __restrict__ V, int64_t ldv, int64_t n,
-                                            double* __restrict__ x, const GmRes& g, int bid, int nblk) {
+                                            double* __restrict__ x, const GmRes& g, int bid, int nblk,
+                                            bool overwrite) {
   constexpr int MX = RSFDE_MAX_RESTART;
   __shared__ GmOut o;
   __shared__ GmCol col;
@@ -470,7 +471,7 @@ __device__ __forceinline__ void update_body(const double* __restrict__ V, int64_
   double2* __restrict__ x2 = (double2*)x;
   const double2* __restrict__ V2 = (const double2*)V;
   for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    double2 xi = x2[i];
+    double2 xi = overwrite ? double2{0.0, 0.0} : x2[i];
     for (int lb = 0; lb < k; lb += 8) {
       double2 v[8];
       ld_cols<8>(v, V2, ld2, i, lb, k);
@@ -484,7 +485,7 @@ __device__ __forceinline__ void update_body(const double* __restrict__ V, int64_
     x2[i] = xi;
   }
   if ((n & 1) && bid == 0 && threadIdx.x == 0) {
-    double xi = x[n - 1];
+    double xi = overwrite ? 0.0 : x[n - 1];
     for (int lb = 0; lb < k; lb += 8) {
       double v[8];
       ld_cols<8>(v, V, ldv, n - 1, lb, k);
@@ -498,8 +499,8 @@ __device__ __forceinline__ void update_body(const double* __restrict__ V, int64_
 
 __global__ void __launch_bounds__(256)
 k_update(const double* __restrict__ V, int64_t ldv, int64_t n, double* __restrict__ x,
-         const GmRes g) {
-  update_body(V, ldv, n, x, g, blockIdx.x, gridDim.x);
+         const GmRes g, int overwrite) {
+  update_body(V, ldv, n, x, g, blockIdx.x, gridDim.x, overwrite != 0);
 }
 
 __global__ void k_state_reset(GmresState* st) {
@@ -554,9 +555,10 @@ hipError_t kry_sweep(int which, const KryArgs& a, hipStream_t s, hipEvent_t ea, 
 }
 
 hipError_t kry_update(const double* V, int64_t ldv, int64_t n, double* x, const GmRes& g,
-                      hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
+                      hipStream_t s, hipEvent_t ea, hipEvent_t eb, int overwrite) {
   const int nb = upd_blocks(n);
-  hipExtLaunchKernelGGL(k_update, dim3((unsigned)nb), dim3(256), 0, s, ea, eb, 0, V, ldv, n, x, g);
+  hipExtLaunchKernelGGL(k_update, dim3((unsigned)nb), dim3(256), 0, s, ea, eb, 0, V, ldv, n, x, g,
+                        overwrite);
   return hipGetLastError();
 }
 
@@ -597,7 +599,7 @@ __global__ void __launch_bounds__(256) k_update_b(const KLaunch kl) {
   g.j = kl.j;
   g.pend = kl.pend;
   g.m = d.k.m;
-  update_body(d.k.V, d.k.ldv, d.k.n, d.x, g, (int)blockIdx.x - kl.start[slot], d.nbu);
+  update_body(d.k.V, d.k.ldv, d.k.n, d.x, g, (int)blockIdx.x - kl.start[slot], d.nbu, d.overwrite != 0);
 }
 
 __global__ void __launch_bounds__(1024) k_norm_part_b(const KLaunch kl) {

@@ -34,7 +34,8 @@ enum : int {
   FL_IN64 = 4,           // in_c holds FP64 values (else the pass precision)
   FL_OUT64 = 8,          // out_a receives FP64 values (else the pass precision)
   FL_FIRST_IS_LAST = 16, // MV_LAST of a one-axis problem: stencil input is e .* v
-  FL_NO_E = 32           // first operator pass: the B (e .* v) term is dropped (S v alone)
+  FL_NO_E = 32,          // first operator pass: the B (e .* v) term is dropped (S v alone)
+  FL_ACCUM = 64          // OP_DST / OP_DSD: add the result to out_a instead of storing it
 };
 
 struct PassArgs {
@@ -105,6 +106,18 @@ __device__ __forceinline__ void st_any(void* p, int64_t i, R v, bool is64) {
   } else {
     if (is64) ((double*)p)[i] = (double)v;
     else ((R*)p)[i] = v;
+  }
+}
+
+// out[i] += v, in out's precision (FL_ACCUM)
+template <typename R>
+__device__ __forceinline__ void st_acc(void* p, int64_t i, R v, bool is64) {
+  if (is64) {
+    double* q = (double*)p + i;
+    *q = *q + (double)v;
+  } else {
+    R* q = (R*)p + i;
+    *q = *q + v;
   }
 }
 
@@ -450,6 +463,17 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
     // 2 DST(x0) = -Im Z_k, 2 DST(x1) = Re Z_k at k = t + T i (1 <= k <= N)
     const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
     const int64_t b0 = c_row(0) * N - 1, b1 = c_row(1) * N - 1;
+    if (a.flags & FL_ACCUM) {
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int k = t + i * T;
+        if (k >= 1) {
+          if (v0) st_acc<R>(a.out_a, b0 + k, -c[i].y, out64);
+          if (v1) st_acc<R>(a.out_a, b1 + k, c[i].x, out64);
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
       const int k = t + i * T;
@@ -783,6 +807,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
       }
     }
   } else {
+    const bool acc = (a.flags & FL_ACCUM) != 0;
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
       int p, pp;
@@ -791,7 +816,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid) 
         const LdsSeq<R, L> bb{lds + (pp >> 1) * LP};
         // component pp&1 of the packed transform: -Im for the first pencil, Re for the second
         const R z = bb.comp(p + 1, (pp & 1) ^ 1);
-        st_any<R>(a.out_a, gbase + (int64_t)p * inner + pp, (pp & 1) ? z : -z, out64);
+        const int64_t g = gbase + (int64_t)p * inner + pp;
+        if (acc) st_acc<R>(a.out_a, g, (pp & 1) ? z : -z, out64);
+        else st_any<R>(a.out_a, g, (pp & 1) ? z : -z, out64);
       }
     }
   }
@@ -818,7 +845,9 @@ rsfde_dst_kernel(const PassArgs a) {
 // device memory; the fields that move with the Arnoldi index j are patched in
 // the kernel from the launch's j (the basis column read or written, the step of
 // the Givens resolve, the status word that stops speculative launches).
-enum : int { BP_IN_J = 1, BP_OUT_J = 2, BP_GM = 4, BP_STOP = 8 };
+// BP_STOP_PEND: passes that run before the step's resolve (the two-sided form's
+// right factor) stop on the status of the pending step, or of step j without one.
+enum : int { BP_IN_J = 1, BP_OUT_J = 2, BP_GM = 4, BP_STOP = 8, BP_STOP_PEND = 16 };
 struct BPass {
   PassArgs a;    // arguments as for Arnoldi step 0
   int64_t ldv;   // basis leading dimension (element offset per step)
@@ -847,6 +876,7 @@ rsfde_pass_batched(const BLaunch bl) {
     a.gm.pend = bl.pend;
   }
   if (d.patch & BP_STOP) a.stop_fl = a.stop_fl + bl.j;
+  if (d.patch & BP_STOP_PEND) a.stop_fl = a.stop_fl + (bl.pend >= 0 ? bl.pend : bl.j);
   pass_body<R, L, F, STRIDED, MODE>(a, (int64_t)blockIdx.x - bl.start[slot]);
 }
 

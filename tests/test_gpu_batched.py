@@ -26,11 +26,11 @@ def _c4_small(k, M=3, sizes=SIZES):
     return [with_grid(insts[i], sizes[i % len(sizes)], M=M) for i in range(k)]
 
 
-def _solve(insts, batched, precision=R.RSFDE_FP64):
+def _solve(insts, batched, precision=R.RSFDE_FP64, method=R.RSFDE_OPGM):
     old = os.environ.get("RSFDE_NO_BATCH")
     os.environ["RSFDE_NO_BATCH"] = "0" if batched else "1"
     try:
-        S = R.Solver([R.params_from_instance(i, precision=precision) for i in insts])
+        S = R.Solver([R.params_from_instance(i, precision=precision, method=method) for i in insts])
     finally:
         if old is None:
             del os.environ["RSFDE_NO_BATCH"]
@@ -57,6 +57,39 @@ def test_batched_equals_one_at_a_time_fp64():
         say(f"   inst {k}: iters {st1[k]['iters']} / {st0[k]['iters']}, equal {np.array_equal(g1[k], g0[k])}")
         assert st1[k]["iters"] == st0[k]["iters"]
         assert st1[k]["converged"] == 1
+        assert np.array_equal(g1[k], g0[k])
+
+
+def test_batched_two_sided_equals_one_at_a_time_and_oracle():
+    """The two-sided form (eq. Pls) batched: the right factor before each step's
+    resolve stops on the pending step's status, the update lands in a temporary
+    and P^{-1/2} of it is added to u by one batched chain; bit for bit as one at
+    a time, and against the oracle's two-sided GMRES."""
+    insts = _c4_small(6)
+    say(f"[batched tpgm] {len(insts)} instances {[i.n for i in insts]}")
+    s1, st1, g1 = _solve(insts, batched=True, method=R.RSFDE_TPGM)
+    s0, st0, g0 = _solve(insts, batched=False, method=R.RSFDE_TPGM)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    for k, inst in enumerate(insts):
+        ref = O.run(inst, two_sided=True)
+        d = rel(g1[k], ref["u"])
+        say(f"   inst {k}: iters {st1[k]['iters']} / {st0[k]['iters']} oracle {sum(ref['iters'])}, "
+            f"rel diff {d:.2e}, equal {np.array_equal(g1[k], g0[k])}")
+        assert st1[k]["iters"] == st0[k]["iters"]
+        assert np.array_equal(g1[k], g0[k])
+        assert d <= 1e-10
+
+
+def test_batched_two_sided_restarts_and_uneven_tolerances():
+    insts = [replace(i, restart=3, max_cycles=40, rtol=t)
+             for i, t in zip(_c4_small(4, M=2), (1e-6, 1e-10, 1e-8, 1e-11))]
+    s1, st1, g1 = _solve(insts, batched=True, method=R.RSFDE_TPGM)
+    s0, st0, g0 = _solve(insts, batched=False, method=R.RSFDE_TPGM)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    say(f"   cycles {[st1[k]['cycles'] for k in range(4)]}")
+    assert max(st1[k]["cycles"] for k in range(4)) > 2
+    for k in range(len(insts)):
+        assert st1[k]["iters"] == st0[k]["iters"]
         assert np.array_equal(g1[k], g0[k])
 
 
