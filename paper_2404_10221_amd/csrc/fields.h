@@ -83,4 +83,3 @@ hipError_t minmax_accum(const double* e, int64_t n, double* mm, double* partial,
                         hipStream_t s);
 hipError_t convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* x, int64_t n, double v, hipStream_t s);
-hipError_t axpy_f64(const double* x, double* y, int64_t n, hipStream_t s);  // y += x

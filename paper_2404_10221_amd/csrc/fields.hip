@@ -450,19 +450,6 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
 }
 
-__global__ void k_axpy(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] += x[i];
-}
-
-hipError_t axpy_f64(const double* x, double* y, int64_t n, hipStream_t s) {
-  int64_t b = (n + 1023) / 1024;
-  if (b > 4096) b = 4096;
-  if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_axpy, dim3((unsigned)b), dim3(256), 0, s, x, y, n);
-  return hipGetLastError();
-}
-
 hipError_t fill_f64(double* x, int64_t n, double v, hipStream_t s) {
   int64_t b = (n + 1023) / 1024;
   if (b > 4096) b = 4096;
