@@ -73,7 +73,7 @@ static hipError_t scratch_ptr(void** out) {
   hipError_t launch_spectrum_L<L>(const double*, int, const cpx<double>*, double*, float*,  \
                                   double*, hipStream_t);                                     \
   template <>                                                                                \
-  hipError_t launch_dht_L<L>(const DhtArgs&, int64_t, hipStream_t);                          \
+  hipError_t launch_dht_L<L>(const DhtArgs&, hipStream_t);                          \
   template <>                                                                                \
   hipError_t launch_dht_tables_L<L>(int, const cpx<double>*, cpx<double>*, cpx<double>*,     \
                                     hipStream_t);
@@ -143,11 +143,11 @@ static bool pass_plan_rt(int L, int var, int* code, int* radix, int* nstage) {
   return false;
 }
 
-static hipError_t launch_dht(int L, const DhtArgs& a, int64_t nblocks, hipStream_t s) {
+static hipError_t launch_dht(int L, const DhtArgs& a, hipStream_t s) {
   switch (L) {
 #define RSFDE_CASE(LL) \
   case LL:             \
-    return launch_dht_L<LL>(a, nblocks, s);
+    return launch_dht_L<LL>(a, s);
     RSFDE_FOR_EACH_L(RSFDE_CASE)
 #undef RSFDE_CASE
   }
@@ -673,8 +673,6 @@ static int run_strang_prec(rsfde_ctx* h, const Inst& I, const double* r, int ri,
     for (int l = 0; l < axis; ++l) inner *= I.ax[l].N;
     a.inner = inner;
     a.npencil = I.n / A.N;
-    a.npairs = (a.npencil + 1) / 2;
-    a.xcd_remap = axis > 0 ? 1 : 0;
     a.chirp = A.chirp;
     a.khat = A.khat;
     a.tw = A.tw64;
@@ -692,8 +690,6 @@ static int run_strang_prec(rsfde_ctx* h, const Inst& I, const double* r, int ri,
     DhtArgs b = a;
     b.in = (const double*)in;
     b.out = o;
-    const int64_t nb = b.xcd_remap ? (b.npairs + 7) / 8 * 8 : b.npairs;
-    if (nb > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
     const int L = I.ax[b.axis].L;
     return timed_launch(h, b.op == DHT_SCALE ? RSFDE_K_DSD : RSFDE_K_DST, 16.0 * (double)I.n,
                         [&](hipEvent_t ea, hipEvent_t eb) -> hipError_t {
@@ -701,7 +697,7 @@ static int run_strang_prec(rsfde_ctx* h, const Inst& I, const double* r, int ri,
                             hipError_t e = hipEventRecord(ea, h->stream);
                             if (e != hipSuccess) return e;
                           }
-                          hipError_t e = launch_dht(L, b, nb, h->stream);
+                          hipError_t e = launch_dht(L, b, h->stream);
                           if (e == hipSuccess && eb) e = hipEventRecord(eb, h->stream);
                           return e;
                         });

@@ -17,6 +17,7 @@
 #pragma once
 #include "fft.h"
 #include "krylov.h"
+#include "pass.h"  // LdsPitch, set_comp
 
 enum : int { DHT_PLAIN = 0, DHT_SCALE = 1 };
 
@@ -25,8 +26,9 @@ struct DhtArgs {
   int N, d, axis;
   int64_t inner;              // element stride of the pass axis
   int64_t npencil;            // pencils (= n / N)
-  int64_t npairs;             // pencil pairs (workgroups that do work)
-  int xcd_remap;              // strided axes: consecutive pairs on one XCD
+  int64_t tiles_inner;        // strided axes: tiles across the inner index range (launcher)
+  int64_t ntiles;             // tiles of 2F pencils (set by the launcher)
+  int xcd_remap;              // strided axes: consecutive tiles on one XCD
   int pad;
   const double* in;
   double* out;
@@ -39,6 +41,20 @@ struct DhtArgs {
   const double* ebar;
   double pscale;              // 1 / prod_l N_l
   const int* stop_fl;         // exit unless *stop_fl == running (NULL: always run)
+};
+
+// Pencil pairs per workgroup of the Hartley passes: up to 512 threads, within
+// the LDS left after the twiddle table.
+template <int L>
+struct DhtShape {
+  static constexpr int T = FftPlan<L>::T;
+  static constexpr int bytes_per_seq =
+      (LdsSeq<double, L>::size + LdsPitch<double, L, 1>::M) * (int)sizeof(cpx<double>);
+  static constexpr int cap = 160 * 1024 - TwHalf<double, L>::size * (int)sizeof(cpx<double>) - 2048;
+  static constexpr int want = 512 / T > 1 ? 512 / T : 1;
+  static constexpr int lim = cap / bytes_per_seq;
+  static constexpr int F = want < lim ? want : (lim > 0 ? lim : 1);
+  static constexpr int NT = F * T;
 };
 
 // H of the two real pencils packed in buf (x in .x, y in .y, entries [0, N)),
@@ -101,89 +117,128 @@ __device__ __forceinline__ void dht_pair(const LdsSeq<double, L> buf, int t, con
   __syncthreads();
 }
 
-template <int L>
+// One tile of 2F pencils (F packed pairs, one LDS sequence each).  Strided axes:
+// the tile is 2F adjacent pencils of one outer index, loaded and stored as row
+// segments across the pencils (lanes over pencils); the contiguous axis: 2F
+// consecutive rows, each pair's thread group reading along its rows.
+template <int L, int F, bool STRIDED>
 __device__ __forceinline__ void dht_body(const DhtArgs& a) {
-  constexpr int T = FftPlan<L>::T;
+  constexpr int T = FftPlan<L>::T, NT = F * T, PT = 2 * F;
   constexpr int KS = (L + T - 1) / T;
-  __shared__ cpx<double> lds[LdsSeq<double, L>::size];
+  constexpr int LP = LdsPitch<double, L, F>::value;
+  constexpr int NE = (L / 2 * PT + NT - 1) / NT;  // strided slots per thread (N < L/2)
+  __shared__ cpx<double> lds[F * LP];
   __shared__ cpx<double> twl[TwHalf<double, L>::size];
-  const int t = threadIdx.x;
-  const LdsSeq<double, L> buf{lds};
-  double twr[TwFill<double, L, T>::C], twi[TwFill<double, L, T>::C];
-  tw_load<double, L, T>(twr, twi, a.tw, t);
+  const int tid = threadIdx.x;
+  const int f = tid / T, t = tid - f * T;
+  const LdsSeq<double, L> buf{lds + f * LP};
+  double twr[TwFill<double, L, NT>::C], twi[TwFill<double, L, NT>::C];
+  tw_load<double, L, NT>(twr, twi, a.tw, tid);
 
-  int64_t pair = blockIdx.x;
+  int64_t tile = blockIdx.x;
   if (a.xcd_remap) {
-    const int64_t b = blockIdx.x, tpx = (a.npairs + 7) >> 3;
-    pair = (b & 7) * tpx + (b >> 3);
+    const int64_t b = blockIdx.x, tpx = (a.ntiles + 7) >> 3;
+    tile = (b & 7) * tpx + (b >> 3);
   }
-  if (pair >= a.npairs) return;                      // the same in every thread
+  if (tile >= a.ntiles) return;                       // the same in every thread
   if (a.stop_fl && *a.stop_fl != GM_RUNNING) return;  // the same in every thread
 
   const int N = a.N;
   const int64_t inner = a.inner;
-  const int64_t p0 = 2 * pair, p1 = 2 * pair + 1;
-  const bool v1 = p1 < a.npencil;
-  auto base = [&](int64_t p) -> int64_t {
-    const int64_t o = p / inner, r = p - o * inner;
-    return o * (int64_t)N * inner + r;
-  };
-  const int64_t b0 = base(p0), b1 = v1 ? base(p1) : b0;
-  tw_store<double, L, T>(twr, twi, twl, t);
+  int64_t gbase = 0, row0 = 0;
+  int nvalid;
+  if constexpr (STRIDED) {
+    const int64_t o = tile / a.tiles_inner;
+    const int64_t pin0 = (tile - o * a.tiles_inner) * PT;
+    const int64_t rem = inner - pin0;
+    nvalid = rem < PT ? (int)rem : PT;
+    gbase = o * (int64_t)N * inner + pin0;
+  } else {
+    row0 = tile * PT;
+    const int64_t rem = a.npencil - row0;
+    nvalid = rem < PT ? (int)rem : PT;
+  }
+  tw_store<double, L, NT>(twr, twi, twl, tid);
+  if constexpr (STRIDED) {
 #pragma unroll
-  for (int i = 0; i < KS; ++i) {
-    const int n = t + i * T;
-    if (n < N) {
-      const double x = a.in[b0 + n * inner];
-      const double y = v1 ? a.in[b1 + n * inner] : 0.0;
-      buf[n] = cpx<double>{x, y};
+    for (int i = 0; i < NE; ++i) {
+      const int flat = tid + i * NT;
+      const int p = flat / PT, pp = flat - p * PT;
+      if (p < N) {
+        const double x = pp < nvalid ? a.in[gbase + (int64_t)p * inner + pp] : 0.0;
+        const LdsSeq<double, L> bb{lds + (pp >> 1) * LP};
+        set_comp(bb[p], pp & 1, x);
+      }
+    }
+  } else {
+    const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+    const int64_t b0 = (row0 + 2 * f) * N, b1 = (row0 + 2 * f + 1) * N;
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+      const int n = t + i * T;
+      if (n < N) buf[n] = cpx<double>{v0 ? a.in[b0 + n] : 0.0, v1 ? a.in[b1 + n] : 0.0};
     }
   }
   __syncthreads();
   const TwHalf<double, L> tw{twl};
   dht_pair<L>(buf, t, tw, a);
-  if (a.op == DHT_SCALE) {
-    // 1/(prod N_l m_J): axis 0 runs along the pencil, the other axes are already
-    // transformed; m_J = (prod_l b_l) (ebar + sum_l eta_l sigma_l / b_l)
-    double lam_o[2] = {1.0, 1.0}, sig_o[2] = {0.0, 0.0};
+  if constexpr (!STRIDED) {
+    if (a.op == DHT_SCALE) {
+      // 1/(prod N_l m_J): axis 0 runs along the pencil, the other axes are already
+      // transformed; m_J = (prod_l b_l) (ebar + sum_l eta_l sigma_l / b_l)
+      double lam_o[2] = {1.0, 1.0}, sig_o[2] = {0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      int64_t rr = c == 0 ? p0 : (v1 ? p1 : p0);
-      for (int l = 1; l < a.d; ++l) {
-        const int64_t j = rr % a.Nax[l];
-        rr /= a.Nax[l];
-        lam_o[c] *= a.lam[l][j];
-        sig_o[c] += a.wq[l][j];
+      for (int c = 0; c < 2; ++c) {
+        int64_t rr = row0 + 2 * f + c;
+        if (rr >= a.npencil) rr = row0 + 2 * f;
+        for (int l = 1; l < a.d; ++l) {
+          const int64_t j = rr % a.Nax[l];
+          rr /= a.Nax[l];
+          lam_o[c] *= a.lam[l][j];
+          sig_o[c] += a.wq[l][j];
+        }
       }
+      const double eb = *a.ebar, ps = a.pscale;
+#pragma unroll
+      for (int i = 0; i < KS; ++i) {
+        const int k = t + i * T;
+        if (k < N) {
+          const double l0 = a.lam[0][k], w0 = a.wq[0][k];
+          const cpx<double> v = buf[k];
+          buf[k] = cpx<double>{v.x * (ps / (lam_o[0] * l0 * (eb + w0 + sig_o[0]))),
+                               v.y * (ps / (lam_o[1] * l0 * (eb + w0 + sig_o[1])))};
+        }
+      }
+      __syncthreads();
+      dht_pair<L>(buf, t, tw, a);
     }
-    const double eb = *a.ebar, ps = a.pscale;
+    const bool v0 = 2 * f < nvalid, v1 = 2 * f + 1 < nvalid;
+    const int64_t b0 = (row0 + 2 * f) * N, b1 = (row0 + 2 * f + 1) * N;
 #pragma unroll
     for (int i = 0; i < KS; ++i) {
-      const int k = t + i * T;
-      if (k < N) {
-        const double l0 = a.lam[0][k], w0 = a.wq[0][k];
-        const cpx<double> v = buf[k];
-        buf[k] = cpx<double>{v.x * (ps / (lam_o[0] * l0 * (eb + w0 + sig_o[0]))),
-                             v.y * (ps / (lam_o[1] * l0 * (eb + w0 + sig_o[1])))};
+      const int n = t + i * T;
+      if (n < N) {
+        const cpx<double> v = buf[n];
+        if (v0) a.out[b0 + n] = v.x;
+        if (v1) a.out[b1 + n] = v.y;
       }
     }
-    __syncthreads();
-    dht_pair<L>(buf, t, tw, a);
-  }
+  } else {
 #pragma unroll
-  for (int i = 0; i < KS; ++i) {
-    const int n = t + i * T;
-    if (n < N) {
-      const cpx<double> v = buf[n];
-      a.out[b0 + n * inner] = v.x;
-      if (v1) a.out[b1 + n * inner] = v.y;
+    for (int i = 0; i < NE; ++i) {
+      const int flat = tid + i * NT;
+      const int p = flat / PT, pp = flat - p * PT;
+      if (p < N && pp < nvalid) {
+        const LdsSeq<double, L> bb{lds + (pp >> 1) * LP};
+        a.out[gbase + (int64_t)p * inner + pp] = bb.comp(p, pp & 1);
+      }
     }
   }
 }
 
-template <int L>
-__global__ void __launch_bounds__(FftPlan<L>::T) k_dht(const DhtArgs a) {
-  dht_body<L>(a);
+template <int L, int F, bool STRIDED>
+__global__ void __launch_bounds__(F * FftPlan<L>::T) k_dht(const DhtArgs a) {
+  dht_body<L, F, STRIDED>(a);
 }
 
 // Setup of one axis: the chirp w_n and the transform of its length-L cyclic
@@ -230,15 +285,32 @@ k_strang_eigs(int N, double alpha, double eta, const double* __restrict__ s, dou
               double* __restrict__ wq);
 
 template <int L>
-hipError_t launch_dht_L(const DhtArgs& a, int64_t nblocks, hipStream_t st);
+hipError_t launch_dht_L(const DhtArgs& a, hipStream_t st);
 template <int L>
 hipError_t launch_dht_tables_L(int N, const cpx<double>* tw, cpx<double>* chirp, cpx<double>* khat,
                                hipStream_t st);
 
 #define RSFDE_INSTANTIATE_DHT(LL)                                                               \
   template <>                                                                                   \
-  hipError_t launch_dht_L<LL>(const DhtArgs& a, int64_t nblocks, hipStream_t st) {              \
-    hipLaunchKernelGGL((k_dht<LL>), dim3((unsigned)nblocks), dim3(FftPlan<LL>::T), 0, st, a);   \
+  hipError_t launch_dht_L<LL>(const DhtArgs& a0, hipStream_t st) {                              \
+    using S = DhtShape<LL>;                                                                     \
+    DhtArgs a = a0;                                                                             \
+    const bool strided = a.axis > 0;                                                            \
+    if (strided) {                                                                              \
+      a.tiles_inner = (a.inner + 2 * S::F - 1) / (2 * S::F);                                    \
+      a.ntiles = (a.npencil / a.inner) * a.tiles_inner;                                         \
+    } else {                                                                                    \
+      a.tiles_inner = 1;                                                                        \
+      a.ntiles = (a.npencil + 2 * S::F - 1) / (2 * S::F);                                       \
+    }                                                                                           \
+    a.xcd_remap = strided ? 1 : 0;                                                              \
+    const int64_t nb = strided ? (a.ntiles + 7) / 8 * 8 : a.ntiles;                             \
+    if (nb <= 0) return hipSuccess;                                                             \
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;                                         \
+    if (strided)                                                                                \
+      hipLaunchKernelGGL((k_dht<LL, S::F, true>), dim3((unsigned)nb), dim3(S::NT), 0, st, a);   \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_dht<LL, S::F, false>), dim3((unsigned)nb), dim3(S::NT), 0, st, a);  \
     return hipGetLastError();                                                                   \
   }                                                                                             \
   template <>                                                                                   \
