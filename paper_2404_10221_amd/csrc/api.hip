@@ -1161,6 +1161,18 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
       if (S.flag == GM_CONVERGED) status = RSFDE_OK;
       break;
     }
+    if (mixed && cyc > 0) {
+      // a refinement sweep's start usually finds the FP64 residual below the bound
+      // already (the previous inner solve reached it): read the start's status
+      // before launching steps, which would otherwise run a whole chunk of
+      // speculative steps that exit only after loading their tiles
+      CKS(read_summary(h, I, &S));
+      if (S.flag == GM_NONFINITE) return RSFDE_E_NONFINITE;
+      if (S.flag == GM_CONVERGED) {
+        status = RSFDE_OK;
+        break;
+      }
+    }
     CKS(run_cycle(h, I, mixed, u, &S));
     if (S.flag == GM_NONFINITE) return RSFDE_E_NONFINITE;
     st.iters += S.k;
@@ -1608,20 +1620,27 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
     }
     std::vector<int> go;  // instances that run a cycle now
     if (mixed) {
-      // instances at their last outer sweep only check the refined residual
+      // instances at their last outer sweep only check the refined residual; a
+      // refinement sweep's start (cyc >= 1) usually finds it below the bound
+      // already, so the starts are read before any steps are launched
       bool any_final = false;
       for (int i : act) {
         const int max_outer = h->inst[i].p.max_outer > 0 ? h->inst[i].p.max_outer : 30;
         if (cyc == max_outer) any_final = true;
       }
-      if (any_final) {
+      if (any_final || cyc > 0) {
         CKS(read_summaries(h, bp->kp));
         for (size_t s = 0; s < act.size(); ++s) {
           const int i = act[s];
           const int max_outer = h->inst[i].p.max_outer > 0 ? h->inst[i].p.max_outer : 30;
+          const GmresSummary& G = h->psum[s];
+          if (G.flag == GM_NONFINITE) return RSFDE_E_NONFINITE;
           if (cyc == max_outer) {
-            last[i] = h->psum[s];
-            if (h->psum[s].flag == GM_CONVERGED) status[i] = RSFDE_OK;
+            last[i] = G;
+            if (G.flag == GM_CONVERGED) status[i] = RSFDE_OK;
+          } else if (G.flag == GM_CONVERGED) {
+            last[i] = G;
+            status[i] = RSFDE_OK;
           } else {
             go.push_back(i);
           }
