@@ -235,7 +235,10 @@ struct Inst {
   double* fsin_e[3] = {nullptr, nullptr, nullptr};
   double* fsin_f[3] = {nullptr, nullptr, nullptr};
   double* fax[3] = {nullptr, nullptr, nullptr};  // per-axis factor tables (AX_ROWS x (N_i+2))
-  int k_prev = 4;
+  // Arnoldi steps of the last cycle that ran at each cycle index of a step (the
+  // first chunk of the next such cycle): the mixed form's two refinement sweeps
+  // need different counts (about 5 and 6-7 on the benchmark grids)
+  int k_prev[3] = {4, 4, 4};
   std::vector<hipGraphExec_t> gexec;  // captured Arnoldi steps: [2 j + (resolve pending)]
   const void* g_e = nullptr;           // e the captured steps read
   int var[3][2][2] = {};  // tile variant per axis, precision (FP64, FP32) and pass class
@@ -1003,12 +1006,12 @@ static void graphs_clear(std::vector<hipGraphExec_t>& cache) {
   cache.clear();
 }
 
-static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* S) {
+static int run_cycle(rsfde_ctx* h, Inst& I, bool fp32, double* x, GmresSummary* S, int cyc) {
   const int m = I.p.restart;
   const int nb = I.nb;
   int j = 0;
   int pending = -1;  // step the next first pass must resolve (-1: already resolved)
-  int chunk = std::max(1, std::min(m, I.k_prev));
+  int chunk = std::max(1, std::min(m, I.k_prev[std::min(cyc, 2)]));
   while (true) {
     const int jend = std::min(m, j + chunk);
     for (int jj = j; jj < jend; ++jj) {
@@ -1173,12 +1176,12 @@ static int step_one(rsfde_ctx* h, Inst& I, const double* e_half, const double* f
         break;
       }
     }
-    CKS(run_cycle(h, I, mixed, u, &S));
+    CKS(run_cycle(h, I, mixed, u, &S, cyc));
     if (S.flag == GM_NONFINITE) return RSFDE_E_NONFINITE;
     st.iters += S.k;
     if (S.k > 0) {
       st.cycles += 1;
-      I.k_prev = S.k;
+      I.k_prev[std::min(cyc, 2)] = S.k;
     }
     if (mixed) {
       // the cycle start just run found the FP64 residual below the bound
@@ -1499,10 +1502,10 @@ static int read_summaries(rsfde_ctx* h, const KPlan& kp) {
 // kernels exit on its status words) but its update is masked off, so V y is
 // added exactly once.
 static int run_cycle_batched(rsfde_ctx* h, const std::vector<int>& S, bool fp32, BPlan& bp,
-                             std::vector<GmresSummary>& fin) {
+                             std::vector<GmresSummary>& fin, int cyc) {
   (void)fp32;
   int kprev = 1;
-  for (int i : S) kprev = std::max(kprev, h->inst[i].k_prev);
+  for (int i : S) kprev = std::max(kprev, h->inst[i].k_prev[std::min(cyc, 2)]);
   const int ns = (int)S.size();
   for (int s = 0; s < ns; ++s) h->pmask[s] = 1;
   CK(hipMemcpyAsync(h->dmask, h->pmask, ns * sizeof(int), hipMemcpyHostToDevice, h->stream));
@@ -1658,7 +1661,7 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
     if (go.empty()) break;
     std::vector<GmresSummary> fin(C);
     memset(fin.data(), 0, sizeof(GmresSummary) * C);
-    CKS(run_cycle_batched(h, go, mixed, *bp, fin));
+    CKS(run_cycle_batched(h, go, mixed, *bp, fin, cyc));
     if (h->inst[0].p.method == RSFDE_TPGM) {
       // u += P^{-1/2} (V y) for the instances whose cycle ended with an update: one
       // batched chain of the right factor whose last pass adds into u (plan region 1
@@ -1686,7 +1689,7 @@ static int step_batched(rsfde_ctx* h, const double* const* e_half, const double*
       st[i].iters += S.k;
       if (S.k > 0) {
         st[i].cycles += 1;
-        I.k_prev = S.k;
+        I.k_prev[std::min(cyc, 2)] = S.k;
       }
       bool done = false;
       if (mixed) {
