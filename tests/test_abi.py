@@ -112,6 +112,8 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.rsfde_set_true_residual(None, 1) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_apply_prec_form(None, 0, 1, None, None) == R.RSFDE_E_INVALID_ARG
     assert lib.rsfde_get_pass_shape(None, 0, 0, 0, 0, None, None) == R.RSFDE_E_INVALID_ARG
+    assert lib.rsfde_solve(None, 1, R.SAMPLE_FN(0), None, None, None) == R.RSFDE_E_INVALID_ARG
+    assert lib.rsfde_solve_range(None, 0, 1, R.SAMPLE_FN(0), None, None, None) == R.RSFDE_E_INVALID_ARG
 
 
 def test_params_from_paper_example():
