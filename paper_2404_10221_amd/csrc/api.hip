@@ -75,6 +75,8 @@ static hipError_t scratch_ptr(void** out) {
   template <>                                                                                \
   hipError_t launch_dht_L<L>(const DhtArgs&, hipStream_t);                          \
   template <>                                                                                \
+  hipError_t launch_dht_batched_L<L>(const DBLaunch&, int64_t, bool, hipStream_t);           \
+  template <>                                                                                \
   hipError_t launch_dht_tables_L<L>(int, const cpx<double>*, cpx<double>*, cpx<double>*,     \
                                     hipStream_t);
 RSFDE_FOR_EACH_L(RSFDE_DECL)
@@ -152,6 +154,30 @@ static hipError_t launch_dht(int L, const DhtArgs& a, hipStream_t s) {
 #undef RSFDE_CASE
   }
   return hipErrorInvalidValue;
+}
+
+static hipError_t launch_dht_batched(int L, const DBLaunch& bl, int64_t nblocks, bool strided,
+                                     hipStream_t s) {
+  switch (L) {
+#define RSFDE_CASE(LL) \
+  case LL:             \
+    return launch_dht_batched_L<LL>(bl, nblocks, strided, s);
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// Tile counts of a Hartley pass (in place); returns its launch's blocks.
+static int64_t dht_tiles(int L, DhtArgs& a) {
+  switch (L) {
+#define RSFDE_CASE(LL) \
+  case LL:             \
+    return dht_tiles_L<LL>(a);
+    RSFDE_FOR_EACH_L(RSFDE_CASE)
+#undef RSFDE_CASE
+  }
+  return -1;
 }
 
 hipError_t launch_dht_tables(int L, int N, const cpx<double>* tw64, cpx<double>* chirp,
@@ -275,9 +301,12 @@ struct TimedPass {
 struct BGroup {
   int L = 0, var = 0;
   bool fp32 = false, strided = false;
+  bool dht = false;             // Hartley passes (Strang form): ddesc instead of desc
+  int op = 0;                   // (Hartley passes: DHT_PLAIN or DHT_SCALE)
   int ninst = 0;
   int64_t nblocks = 0;
   const BPass* desc = nullptr;  // device copies (batch descriptor buffer)
+  const DBPass* ddesc = nullptr;
   const int* start = nullptr;
   int cls = 0;
   bool mv = false;  // operator pass (else sine transform); one op per group
@@ -309,6 +338,9 @@ struct RecPass {
   bool fp32;
   int inst;
   bool stop_pend;  // runs before the step's resolve: stops on the pending step's status
+  bool dht = false;  // a Hartley pass (Strang form): da and its launch's blocks dnb
+  DhtArgs da{};
+  int64_t dnb = 0;
 };
 
 struct rsfde_ctx {
@@ -694,6 +726,20 @@ static int run_strang_prec(rsfde_ctx* h, const Inst& I, const double* r, int ri,
     b.in = (const double*)in;
     b.out = o;
     const int L = I.ax[b.axis].L;
+    if (h->rec) {
+      RecPass rp;
+      memset(&rp.a, 0, sizeof(rp.a));
+      rp.a.axis = b.axis;
+      rp.fp32 = false;
+      rp.inst = h->rec_inst;
+      rp.stop_pend = false;
+      rp.dht = true;
+      rp.dnb = dht_tiles(L, b);
+      rp.da = b;
+      if (rp.dnb < 0 || rp.dnb > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
+      h->rec->push_back(rp);
+      return RSFDE_OK;
+    }
     return timed_launch(h, b.op == DHT_SCALE ? RSFDE_K_DSD : RSFDE_K_DST, 16.0 * (double)I.n,
                         [&](hipEvent_t ea, hipEvent_t eb) -> hipError_t {
                           if (ea) {
@@ -1237,8 +1283,7 @@ static bool batchable(const rsfde_ctx* h) {
   // addresses exist in every instance)
   for (const Inst& I : h->inst)
     if (I.d != h->inst[0].d || I.p.precision != h->inst[0].p.precision ||
-        I.p.restart != h->inst[0].p.restart || I.p.method != h->inst[0].p.method ||
-        I.p.method == RSFDE_SPGM)
+        I.p.restart != h->inst[0].p.restart || I.p.method != h->inst[0].p.method)
       return false;
   return true;
 }
@@ -1311,6 +1356,42 @@ static int plan_chain(rsfde_ctx* h, int r, const std::vector<int>& S, RecFn rec_
       g.var = r0.a.var;
       g.fp32 = r0.fp32;
       g.strided = r0.a.axis > 0;
+      g.dht = r0.dht;
+      if (g.dht) {
+        // Hartley passes: grouped by length, axis kind and op
+        g.op = r0.da.op;
+        g.cls = g.op == DHT_SCALE ? RSFDE_K_DSD : RSFDE_K_DST;
+        std::vector<DBPass> ddesc;
+        std::vector<int> start(1, 0);
+        for (size_t s = s0; s < S.size(); ++s) {
+          const RecPass& rp = recs[s][pi];
+          const Inst& I = h->inst[rp.inst];
+          if (used[s] || !rp.dht || I.ax[rp.a.axis].L != g.L || (rp.a.axis > 0) != g.strided ||
+              rp.da.op != g.op)
+            continue;
+          used[s] = 1;
+          DBPass b;
+          memset(&b, 0, sizeof(b));
+          b.a = rp.da;
+          b.ldv = I.ldv;
+          if (oper) {
+            if (rp.da.out == I.V + I.ldv) b.patch |= BP_OUT_J;
+            if (rp.da.stop_fl == &I.st->FL[0]) b.patch |= BP_STOP;
+          }
+          ddesc.push_back(b);
+          const int64_t nb = (rp.dnb + 7) / 8 * 8;
+          if (start.back() + nb > 0x7fffffffLL) return RSFDE_E_UNSUPPORTED;
+          start.push_back((int)(start.back() + nb));
+          g.bytes += 16.0 * (double)I.n;
+        }
+        g.ninst = (int)ddesc.size();
+        g.nblocks = start.back();
+        g.ddesc = (const DBPass*)bappend(h, r, ddesc.data(), ddesc.size() * sizeof(DBPass));
+        g.start = (const int*)bappend(h, r, start.data(), start.size() * sizeof(int));
+        if (!g.ddesc || !g.start) return RSFDE_E_WORKSPACE;
+        out.pos[pi].push_back(g);
+        continue;
+      }
       g.cls = op_class(r0.a.op);
       g.mv = r0.a.op <= OP_MV_LAST;
       std::vector<BPass> desc;
@@ -1318,7 +1399,7 @@ static int plan_chain(rsfde_ctx* h, int r, const std::vector<int>& S, RecFn rec_
       for (size_t s = s0; s < S.size(); ++s) {
         const RecPass& rp = recs[s][pi];
         const Inst& I = h->inst[rp.inst];
-        if (used[s] || I.ax[rp.a.axis].L != g.L || rp.a.var != g.var || rp.fp32 != g.fp32 ||
+        if (used[s] || rp.dht || I.ax[rp.a.axis].L != g.L || rp.a.var != g.var || rp.fp32 != g.fp32 ||
             (rp.a.axis > 0) != g.strided || rp.a.op != r0.a.op)
           continue;
         used[s] = 1;
@@ -1354,6 +1435,23 @@ static int launch_chain_batched(rsfde_ctx* h, const BChain& c, int j, int pend) 
   for (const auto& pos : c.pos)
     for (const BGroup& g : pos) {
       if (g.nblocks <= 0) continue;
+      if (g.dht) {
+        DBLaunch dl;
+        dl.desc = g.ddesc;
+        dl.start = g.start;
+        dl.ninst = g.ninst;
+        dl.j = j;
+        CKS(timed_launch(h, g.cls, g.bytes, [&](hipEvent_t ea, hipEvent_t eb) -> hipError_t {
+          if (ea) {
+            hipError_t e = hipEventRecord(ea, h->stream);
+            if (e != hipSuccess) return e;
+          }
+          hipError_t e = launch_dht_batched(g.L, dl, g.nblocks, g.strided, h->stream);
+          if (e == hipSuccess && eb) e = hipEventRecord(eb, h->stream);
+          return e;
+        }));
+        continue;
+      }
       BLaunch bl;
       bl.desc = g.desc;
       bl.start = g.start;

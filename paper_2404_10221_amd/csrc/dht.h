@@ -122,7 +122,7 @@ __device__ __forceinline__ void dht_pair(const LdsSeq<double, L> buf, int t, con
 // segments across the pencils (lanes over pencils); the contiguous axis: 2F
 // consecutive rows, each pair's thread group reading along its rows.
 template <int L, int F, bool STRIDED>
-__device__ __forceinline__ void dht_body(const DhtArgs& a) {
+__device__ __forceinline__ void dht_body(const DhtArgs& a, const int64_t bid) {
   constexpr int T = FftPlan<L>::T, NT = F * T, PT = 2 * F;
   constexpr int KS = (L + T - 1) / T;
   constexpr int LP = LdsPitch<double, L, F>::value;
@@ -135,10 +135,10 @@ __device__ __forceinline__ void dht_body(const DhtArgs& a) {
   double twr[TwFill<double, L, NT>::C], twi[TwFill<double, L, NT>::C];
   tw_load<double, L, NT>(twr, twi, a.tw, tid);
 
-  int64_t tile = blockIdx.x;
+  int64_t tile = bid;
   if (a.xcd_remap) {
-    const int64_t b = blockIdx.x, tpx = (a.ntiles + 7) >> 3;
-    tile = (b & 7) * tpx + (b >> 3);
+    const int64_t tpx = (a.ntiles + 7) >> 3;
+    tile = (bid & 7) * tpx + (bid >> 3);
   }
   if (tile >= a.ntiles) return;                       // the same in every thread
   if (a.stop_fl && *a.stop_fl != GM_RUNNING) return;  // the same in every thread
@@ -238,7 +238,52 @@ __device__ __forceinline__ void dht_body(const DhtArgs& a) {
 
 template <int L, int F, bool STRIDED>
 __global__ void __launch_bounds__(F * FftPlan<L>::T) k_dht(const DhtArgs a) {
-  dht_body<L, F, STRIDED>(a);
+  dht_body<L, F, STRIDED>(a, blockIdx.x);
+}
+
+// Batched Hartley passes: one launch covers the same pass of many instances that
+// share the transform length and axis kind (tile counts per instance in the
+// descriptors, set by dht_tiles).  The output column and the status word move
+// with the Arnoldi index j of the launch (BP_OUT_J, BP_STOP as for the pencil
+// passes).
+struct DBPass {
+  DhtArgs a;     // arguments as for Arnoldi step 0
+  int64_t ldv;   // basis leading dimension (element offset per step)
+  int patch;     // BP_OUT_J, BP_STOP
+  int pad;
+};
+struct DBLaunch {
+  const DBPass* desc;  // per-instance descriptors, slot order
+  const int* start;    // start[s] = first block of slot s; start[ninst] = grid size
+  int ninst;
+  int j;
+};
+
+template <int L, int F, bool STRIDED>
+__global__ void __launch_bounds__(F * FftPlan<L>::T) k_dht_batched(const DBLaunch bl) {
+  const int slot = batch_slot(bl.start, bl.ninst, blockIdx.x);
+  const DBPass& d = bl.desc[slot];
+  DhtArgs a = d.a;
+  if (d.patch & BP_OUT_J) a.out = a.out + (int64_t)bl.j * d.ldv;
+  if (d.patch & BP_STOP) a.stop_fl = a.stop_fl + bl.j;
+  dht_body<L, F, STRIDED>(a, (int64_t)blockIdx.x - bl.start[slot]);
+}
+
+// Tile counts of a Hartley pass of length L (in place in a); returns the blocks
+// of its launch (XCD rounds on strided axes).
+template <int L>
+inline int64_t dht_tiles_L(DhtArgs& a) {
+  using S = DhtShape<L>;
+  const bool strided = a.axis > 0;
+  if (strided) {
+    a.tiles_inner = (a.inner + 2 * S::F - 1) / (2 * S::F);
+    a.ntiles = (a.npencil / a.inner) * a.tiles_inner;
+  } else {
+    a.tiles_inner = 1;
+    a.ntiles = (a.npencil + 2 * S::F - 1) / (2 * S::F);
+  }
+  a.xcd_remap = strided ? 1 : 0;
+  return strided ? (a.ntiles + 7) / 8 * 8 : a.ntiles;
 }
 
 // Setup of one axis: the chirp w_n and the transform of its length-L cyclic
@@ -287,6 +332,8 @@ k_strang_eigs(int N, double alpha, double eta, const double* __restrict__ s, dou
 template <int L>
 hipError_t launch_dht_L(const DhtArgs& a, hipStream_t st);
 template <int L>
+hipError_t launch_dht_batched_L(const DBLaunch& bl, int64_t nblocks, bool strided, hipStream_t st);
+template <int L>
 hipError_t launch_dht_tables_L(int N, const cpx<double>* tw, cpx<double>* chirp, cpx<double>* khat,
                                hipStream_t st);
 
@@ -295,22 +342,25 @@ hipError_t launch_dht_tables_L(int N, const cpx<double>* tw, cpx<double>* chirp,
   hipError_t launch_dht_L<LL>(const DhtArgs& a0, hipStream_t st) {                              \
     using S = DhtShape<LL>;                                                                     \
     DhtArgs a = a0;                                                                             \
-    const bool strided = a.axis > 0;                                                            \
-    if (strided) {                                                                              \
-      a.tiles_inner = (a.inner + 2 * S::F - 1) / (2 * S::F);                                    \
-      a.ntiles = (a.npencil / a.inner) * a.tiles_inner;                                         \
-    } else {                                                                                    \
-      a.tiles_inner = 1;                                                                        \
-      a.ntiles = (a.npencil + 2 * S::F - 1) / (2 * S::F);                                       \
-    }                                                                                           \
-    a.xcd_remap = strided ? 1 : 0;                                                              \
-    const int64_t nb = strided ? (a.ntiles + 7) / 8 * 8 : a.ntiles;                             \
+    const int64_t nb = dht_tiles_L<LL>(a);                                                      \
     if (nb <= 0) return hipSuccess;                                                             \
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;                                         \
-    if (strided)                                                                                \
+    if (a.axis > 0)                                                                             \
       hipLaunchKernelGGL((k_dht<LL, S::F, true>), dim3((unsigned)nb), dim3(S::NT), 0, st, a);   \
     else                                                                                        \
       hipLaunchKernelGGL((k_dht<LL, S::F, false>), dim3((unsigned)nb), dim3(S::NT), 0, st, a);  \
+    return hipGetLastError();                                                                   \
+  }                                                                                             \
+  template <>                                                                                   \
+  hipError_t launch_dht_batched_L<LL>(const DBLaunch& bl, int64_t nblocks, bool strided,        \
+                                      hipStream_t st) {                                         \
+    using S = DhtShape<LL>;                                                                     \
+    if (strided)                                                                                \
+      hipLaunchKernelGGL((k_dht_batched<LL, S::F, true>), dim3((unsigned)nblocks), dim3(S::NT), \
+                         0, st, bl);                                                            \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_dht_batched<LL, S::F, false>), dim3((unsigned)nblocks),             \
+                         dim3(S::NT), 0, st, bl);                                               \
     return hipGetLastError();                                                                   \
   }                                                                                             \
   template <>                                                                                   \

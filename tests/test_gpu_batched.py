@@ -80,6 +80,37 @@ def test_batched_two_sided_equals_one_at_a_time_and_oracle():
         assert d <= 1e-10
 
 
+def test_batched_strang_equals_one_at_a_time_and_oracle():
+    """The Strang-circulant comparison solver batched: its Hartley passes are
+    recorded into the chain plans like the pencil passes (output column and
+    status word patched per Arnoldi step); bit for bit as one at a time, and
+    against the oracle's Strang GMRES."""
+    insts = _c4_small(5)
+    say(f"[batched spgm] {len(insts)} instances {[i.n for i in insts]}")
+    s1, st1, g1 = _solve(insts, batched=True, method=R.RSFDE_SPGM)
+    s0, st0, g0 = _solve(insts, batched=False, method=R.RSFDE_SPGM)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    for k, inst in enumerate(insts):
+        ref = O.run(inst, strang=True)
+        d = rel(g1[k], ref["u"])
+        say(f"   inst {k}: iters {st1[k]['iters']} / {st0[k]['iters']} oracle {sum(ref['iters'])}, "
+            f"rel diff {d:.2e}, equal {np.array_equal(g1[k], g0[k])}")
+        assert st1[k]["iters"] == st0[k]["iters"]
+        assert np.array_equal(g1[k], g0[k])
+        assert d <= 1e-10
+
+
+def test_batched_strang_restarts():
+    insts = [replace(i, restart=4, max_cycles=60) for i in _c4_small(3, M=2)]
+    s1, st1, g1 = _solve(insts, batched=True, method=R.RSFDE_SPGM)
+    s0, st0, g0 = _solve(insts, batched=False, method=R.RSFDE_SPGM)
+    assert s1 == R.RSFDE_OK and s0 == R.RSFDE_OK
+    assert max(st1[k]["cycles"] for k in range(3)) > 2
+    for k in range(len(insts)):
+        assert st1[k]["iters"] == st0[k]["iters"]
+        assert np.array_equal(g1[k], g0[k])
+
+
 def test_batched_two_sided_restarts_and_uneven_tolerances():
     insts = [replace(i, restart=3, max_cycles=40, rtol=t)
              for i, t in zip(_c4_small(4, M=2), (1e-6, 1e-10, 1e-8, 1e-11))]
