@@ -131,3 +131,18 @@ def test_graph_replay_batched():
     c = _run(insts, graphs=False, fresh_e=True, batched=False)
     _same(a, b)
     _same(a, c)
+
+
+@pytest.mark.parametrize("method", [R.RSFDE_TPGM, R.RSFDE_SPGM], ids=["two_sided", "strang"])
+def test_graph_replay_batched_other_forms(method):
+    # batched two-sided (right factor stopping on the pending step's status) and
+    # Strang (batched Hartley passes) forms replayed from graphs, against direct
+    # batched and one-at-a-time launches
+    sizes = [(15, 31), (31, 15), (23, 23)]
+    c4 = config("C4")
+    insts = [replace(with_grid(c4[i], sizes[i], M=3), restart=5, max_cycles=60) for i in range(3)]
+    a = _run(insts, graphs=True, method=method)
+    b = _run(insts, graphs=False, method=method)
+    c = _run(insts, graphs=False, batched=False, method=method)
+    _same(a, b)
+    _same(a, c)
